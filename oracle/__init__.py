@@ -1,0 +1,128 @@
+"""FP64 CPU oracle for the multideterminant evaluator.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by
+the CPU-baseline leg of the benchmark, never by the product library.  It
+shares no code with the GPU path.
+
+* ``oracle.c`` (built here with gcc into ``liboracle.so``): orbitals, one LU
+  per distinct spin determinant, analytic derivative ratios, Eq. (1) and
+  Eq. (main) sums.
+* ``preprocess.py``: the paper's determinant ordering and sparse indexing
+  (Sec. 2.1), written independently of the library's C++ version.
+* ``brute.py``: brute-force references for tiny inputs.
+* ``mlp.py``, ``vmc.py``: FP64 references for the learned proposal and the
+  Metropolis step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain -O2, OpenMP, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC,
+                               "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("MDET_ORACLE_LIB_OVERRIDE")   # mutation tests only
+        if path is None:
+            path = _LIB
+            if not os.path.exists(path):
+                build()
+        lib = ctypes.CDLL(path)
+        P = ctypes.c_void_p
+        lib.orc_eval.restype = ctypes.c_int
+        lib.orc_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P,
+                                 ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P,
+                                 ctypes.c_int, P, P, P, P, P, ctypes.c_int]
+        lib.orc_orbitals.restype = None
+        lib.orc_orbitals.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
+        lib.orc_slater.restype = ctypes.c_int
+        lib.orc_slater.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def orbitals(wl, r):
+    """[5][n_mo] values, grad x,y,z and Laplacian of every orbital at point r."""
+    lib = _load()
+    pw = np.ascontiguousarray(wl.pow_abc, dtype=np.int32)
+    al = np.ascontiguousarray(wl.alpha, dtype=np.float64)
+    cf = np.ascontiguousarray(wl.coef, dtype=np.float64)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    out = np.zeros((5, wl.n_mo))
+    lib.orc_orbitals(wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf), _p(r), _p(out))
+    return out
+
+
+def slater(S, G):
+    """(sign, ln|det S|, ratio[n][4]) for S [n][n] and G [4][n][n]."""
+    lib = _load()
+    n = S.shape[0]
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    sg = np.zeros(1)
+    la = np.zeros(1)
+    rt = np.zeros((n, 4))
+    work = np.zeros(2 * n * n + n)
+    lib.orc_slater(n, _p(S), _p(G), _p(sg), _p(la), _p(rt), _p(work))
+    return float(sg[0]), float(la[0]), rt
+
+
+class Result:
+    """sign [W], logabs [W], gl [W][N][4], rs_psi [W], rs_gl [W][N][4]."""
+
+    def __init__(self, sign, logabs, gl, rs_psi, rs_gl):
+        self.sign, self.logabs, self.gl, self.rs_psi, self.rs_gl = sign, logabs, gl, rs_psi, rs_gl
+
+
+def evaluate(wl, R=None, max_degree="auto", mode=0, n_threads=0, c=None,
+             det_up=None, det_dn=None):
+    """Evaluate the wavefunction of workload ``wl`` at walkers ``R``.
+
+    mode 0 = Eq. (1) compensated sum over products, 1 = Eq. (main) bilinear form.
+    """
+    lib = _load()
+    R = wl.R if R is None else R
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    W, N = R.shape[0], wl.n_up + wl.n_dn
+    if isinstance(max_degree, str) and max_degree == "auto":
+        max_degree = wl.max_degree
+    md = None if max_degree is None else np.ascontiguousarray(max_degree, dtype=np.int8)
+    c = np.ascontiguousarray(wl.c if c is None else c, dtype=np.float64)
+    du = np.ascontiguousarray(wl.det_up if det_up is None else det_up, dtype=np.uint64)
+    dd = np.ascontiguousarray(wl.det_dn if det_dn is None else det_dn, dtype=np.uint64)
+    pw = np.ascontiguousarray(wl.pow_abc, dtype=np.int32)
+    al = np.ascontiguousarray(wl.alpha, dtype=np.float64)
+    cf = np.ascontiguousarray(wl.coef, dtype=np.float64)
+    sign = np.zeros(W)
+    logabs = np.zeros(W)
+    gl = np.zeros((W, N, 4))
+    rs_psi = np.zeros(W)
+    rs_gl = np.zeros((W, N, 4))
+    rc = lib.orc_eval(wl.n_up, wl.n_dn, wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf), wl.n_int,
+                      int(c.shape[0]), _p(du), _p(dd), _p(c), W, _p(R), _p(md), int(mode),
+                      _p(sign), _p(logabs), _p(gl), _p(rs_psi), _p(rs_gl), int(n_threads))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (code {rc})")
+    return Result(sign, logabs, gl, rs_psi, rs_gl)

@@ -1,0 +1,40 @@
+"""The oracle pins must catch plausible mistakes.  Each case compiles a copy of
+oracle.c with one planted error (CPU only) and checks that the pin suite
+fails against it."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+MUTATIONS = {
+    "gradient_sign": ("double d1 = -2.0 * alpha * ipow(x, a + 1);",
+                      "double d1 = 2.0 * alpha * ipow(x, a + 1);"),
+    "laplacian_dropped_term": ("+ 4.0 * alpha * alpha * ipow(x, a + 2);", ";"),
+    "laplacian_wrong_factor": ("(double)(2 * a + 1)", "(double)(2 * a)"),
+    "inverse_transposed": ("s += X[c * n + e] * G[(q * n + e) * n + c] * cscale[c];",
+                           "s += X[e * n + c] * G[(q * n + e) * n + c] * cscale[c];"),
+    "pivot_sign_dropped": ("if (d < 0) sg = -sg;", ";"),
+    "column_scale_dropped": ("*logabs = la + colexp_sum * log(2.0);", "*logabs = la;"),
+    "wrong_spin_ratio": ("double x = term * rd[e * 4 + q];", "double x = term * rt_u[e * 4 + q];"),
+}
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_mutation(name, tmp_path):
+    old, new = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, name
+    mut_c = tmp_path / "oracle_mut.c"
+    mut_c.write_text(src.replace(old, new))
+    so = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", str(mut_c), "-o", str(so), "-lm"])
+    env = dict(os.environ, MDET_ORACLE_LIB_OVERRIDE=str(so))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, f"mutation {name} survived the pins:\n{r.stdout[-2000:]}"
