@@ -1,0 +1,184 @@
+"""Benchmark: walker-steps/s of the multideterminant evaluation (Psi, grad,
+Laplacian of every electron) on the 1e5-determinant workload
+(9+8 electrons, 100 orbitals, 1000 distinct determinants per spin, 1024
+walkers), mixed precision and FP64, on one GPU.
+
+A step is one call of the whole hot path (orbitals, reference LU, table,
+ratios, sparse combination, derivatives) on a batch of 1024 walkers whose
+coordinates already sit in HBM; a pool of 8 walker batches is rotated so
+consecutive steps see different walkers.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_FP64 = 78.6e12      # FP64 vector (and matrix) flop/s
+PEAK_FP32 = 157.3e12     # FP32 vector flop/s
+PEAK_HBM = 8.0e12        # bytes/s
+
+
+def kernel_model(name, wl, st, W, precision):
+    """Algorithmic flops and HBM bytes of one launch of `name` on W walkers.
+
+    Counts follow the algorithm (no padding, no recomputation): an FMA is 2
+    flops, an exp is counted as 1 flop.  Bytes are the data a kernel must
+    read or write at least once.
+    """
+    n = (wl.n_up, wl.n_dn)
+    M, P, N = wl.n_mo, wl.n_prim, wl.n_up + wl.n_dn
+    U, V, Z = st.n_uniq_up, st.n_uniq_dn, st.n_det
+    degs = (list(st.n_by_degree_up), list(st.n_by_degree_dn))
+    b = 4 if precision == 1 else 8
+    det_flops = {0: 0, 1: 0, 2: 3, 3: 14, 4: 47}
+    cof_flops = {1: 0, 2: 0, 3: 3, 4: 14}
+    if name == "k_spmm":
+        flops = W * (4 * Z + 2 * U)
+        byts = 2 * Z * (b + 4) + 4 * (U + V + 2) + W * (U + V) * 2 * b + W * b
+        return flops, byts, ("fp32" if b == 4 else "fp64")
+    if name == "k_ratios":
+        flops = W * sum(sum(c * det_flops[s] for s, c in enumerate(d)) for d in degs)
+        byts = W * sum(nn * M * 8 for nn in n) + W * (U + V) * b
+        return flops, byts, "fp64"
+    if name == "k_deriv":
+        f = 0
+        for d, nn in zip(degs, n):
+            f += sum(c * s * s * (cof_flops.get(s, 0) + 3) for s, c in enumerate(d) if s > 0)
+            f += 2 * M * nn * nn + 2 * nn * nn * M + 4 * nn * 2 * (M + nn)
+        byts = W * (sum(nn * M * 8 + nn * nn * 8 for nn in n) + (U + V) * b + 4 * N * M * 8
+                    + N * 4 * 8 * 2)
+        return W * f, byts, "fp64"
+    if name == "k_reference":
+        f = N * M * P * 36
+        for nn in n:
+            f += (2 * nn ** 3) // 3 + 2 * nn ** 3 + 4 * nn ** 3 + 2 * nn * nn * M + 8 * nn * nn
+        byts = W * (N * 3 * 8 + 5 * N * M * 8 + 2 * (nn * M * 8))
+        return W * f, byts, "fp64"
+    return 0, 0, "fp64"
+
+
+def run_gpu(wl, precision, steps, warmup, pool):
+    import torch
+    import paper_1510_00730_amd as mdet
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    W, N = wl.R.shape[0], wl.n_elec
+    Rpool = [torch.as_tensor(r, dtype=torch.float64, device="cuda") for r in pool]
+    out = (torch.empty(W, dtype=torch.float64, device="cuda"),
+           torch.empty(W, dtype=torch.float64, device="cuda"),
+           torch.empty((W, N, 4), dtype=torch.float64, device="cuda"),
+           torch.empty(W, dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream()
+    for k in range(warmup):
+        ev.eval_walkers(Rpool[k % len(Rpool)], precision=precision, out=out, stream=stream)
+    torch.cuda.synchronize()
+    ev.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev.eval_walkers(Rpool[k % len(Rpool)], precision=precision, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    times, calls = ev.kernel_times()
+    ev.set_profiling(False)
+    ws = out[3].cpu().numpy()
+    st = ev.stats()
+    ev.close()
+    return (t1 - t0), times, calls, st, ws
+
+
+def cpu_baseline(wl, n_walk):
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    cores = max(1, min(cores, os.cpu_count() or 1))
+    R = wl.R[:n_walk]
+    oracle.evaluate(wl, R[:cores], n_threads=cores)   # warm-up (page-in, thread pool)
+    t0 = time.perf_counter()
+    oracle.evaluate(wl, R, n_threads=cores)
+    dt = time.perf_counter() - t0
+    return {"value": n_walk / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_walk} walkers of the same workload, one evaluation each, FP64 oracle "
+                      f"(one LU per distinct determinant, Eq. (1) compensated sum), {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--cpu-walkers", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); walkers are independent, "
+              "so more GPUs would each run this same per-GPU workload.", file=sys.stderr)
+        sys.exit(2)
+    from gen.workloads import make_config, walker_pool
+    wl = make_config(args.config)
+    pool = walker_pool(wl, 8)
+    prec = 1 if args.precision == "mixed" else 0
+    res = {}
+    for p in (prec, 1 - prec):
+        dt, times, calls, st, ws = run_gpu(wl, p, args.steps, args.warmup, pool)
+        res[p] = dict(dt=dt, times=times, calls=calls, st=st, ws=ws)
+        print(f"[bench] precision {'mixed' if p else 'fp64'}: {args.steps * wl.n_walk / dt:.4g} "
+              f"walker-steps/s, {1e3 * dt / args.steps:.3f} ms/step, kernels (ms/launch): "
+              + ", ".join(f"{k} {v / max(calls, 1):.4f}" for k, v in times.items()),
+              file=sys.stderr, flush=True)
+    r = res[prec]
+    W = wl.n_walk
+    value = args.steps * W / r["dt"]
+    dom = max(r["times"], key=lambda k: r["times"][k])
+    avg_ms = r["times"][dom] / max(r["calls"], 1)
+    flops, byts, kdt = kernel_model(dom, wl, r["st"], W, prec)
+    t = avg_ms * 1e-3
+    peak_f = PEAK_FP32 if kdt == "fp32" else PEAK_FP64
+    if byts / PEAK_HBM >= flops / peak_f:
+        roof = {"bound": "hbm", "achieved": byts / t / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": flops / t / 1e12, "peak": peak_f / 1e12,
+                "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = avg_ms
+    roof["algorithmic_flops"] = flops
+    roof["algorithmic_bytes"] = byts
+    line = {
+        "metric": "walker-steps/s (Psi,∇,∇²) at 1e5 dets: FP64 vs mixed prec at rel err 1e-5",
+        "value": value,
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * r["dt"] / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 sparse combination + f64" if prec == 1 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{wl.name}: 9+8 electrons, 100 orbitals x 4 primitives, "
+                               f"1000+1000 distinct dets, 1e5 products, {W} walkers",
+                   "precision": args.precision, "walker_batch": W,
+                   "fallback_fraction": float(np.mean(r["ws"] == 1))},
+        "fp64_value": args.steps * W / res[0]["dt"],
+        "mixed_value": args.steps * W / res[1]["dt"],
+        "kernel_ms_per_launch": {k: v / max(r["calls"], 1) for k, v in r["times"].items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_walkers)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

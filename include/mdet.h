@@ -70,7 +70,10 @@ enum {
 };
 
 /* Create a context on HIP device `hip_device` (sets it current).  *out is
- * owned by the caller and released with mdet_destroy. */
+ * owned by the caller and released with mdet_destroy.  hip_device == -1 makes
+ * a host-only context: set_expansion pre-processes and get_indexing /
+ * get_stats work, nothing touches a GPU, and eval_walkers returns
+ * MDET_ESTATE. */
 mdet_status mdet_create(mdet_ctx **out, int32_t hip_device);
 
 /* Free every device and host buffer of the context.  Waits for the device. */
@@ -102,8 +105,9 @@ mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim,
  * the earliest one on ties).
  * det_up, det_dn: uint64 [n_det][n_int] host; c: double [n_det] host.
  * Requires mdet_init_orbitals first.  Errors: MDET_ESPIN, MDET_EORBITAL,
- * MDET_EPOPCOUNT, MDET_EDUPLICATE, MDET_EDEGREE, MDET_EDIM (n_up > MDET_MAX_SPIN_ELEC
- * or n_up + n_dn > n_mo... or n_det > 2^31-1).  Synchronous.
+ * MDET_EPOPCOUNT, MDET_EDUPLICATE, MDET_EDEGREE, MDET_EDIM (n_dn < 1,
+ * n_up > MDET_MAX_SPIN_ELEC, n_up > n_mo, or n_det outside 1..2^31-1).
+ * Synchronous.
  */
 mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_t n_int,
                                int64_t n_det, const uint64_t *det_up,
@@ -153,8 +157,9 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
 /*
  * Reference-conditioning threshold: a (walker, spin) whose reference matrix A
  * has ||A||_1 ||A^-1||_1 above kappa_max (or a zero pivot) is evaluated by the
- * direct-LU fallback instead of the table method.  Default 1e3 (FP64) -- the
- * analogue of the paper's 1e-3 ratio rule for its update chain (Sec. 2.2).
+ * direct-LU fallback instead of the table method.  Default 3e4 -- the
+ * analogue of the paper's 1e-3 ratio rule for its update chain (Sec. 2.2):
+ * rounding errors of the table method grow with this condition number.
  */
 mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, double kappa_max);
 
@@ -171,6 +176,22 @@ typedef struct {
 
 /* Shapes and sizes of the loaded expansion. */
 mdet_status mdet_get_stats(const mdet_ctx *ctx, mdet_stats *out);
+
+/*
+ * Per-kernel timing.  With enable != 0, every later mdet_eval_walkers call
+ * records HIP events on its own stream around each of its kernels; the
+ * accumulated times are reset by this call.  Timing adds one event record
+ * per kernel and one wait on the previous call's last event per call.
+ */
+mdet_status mdet_set_profiling(mdet_ctx *ctx, int32_t enable);
+
+/*
+ * Accumulated kernel times (milliseconds, summed over the profiled calls,
+ * host arrays of `capacity` entries, each nullable), the kernel names
+ * (static strings) and counts.  Waits for the last profiled call.
+ */
+mdet_status mdet_get_kernel_times(mdet_ctx *ctx, int32_t capacity, double *ms_total,
+                                  const char **names, int32_t *n_kernels, int64_t *n_calls);
 
 #ifdef __cplusplus
 }

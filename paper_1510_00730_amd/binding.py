@@ -1,0 +1,213 @@
+"""ctypes binding of libmdet (include/mdet.h).  Argument marshalling only:
+every step of the evaluation runs in the HIP kernels of libmdet.so.
+
+PyTorch supplies device memory and the current stream; nothing here falls
+back to a CPU path.  If the library is missing the import of this module
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmdet.so")
+
+MDET_FP64, MDET_MIXED = 0, 1
+W_OK, W_FALLBACK, W_NODE = 0, 1, 2
+MAX_DEGREE = 4
+
+STATUS = {0: "MDET_OK", -1: "MDET_EINVAL", -2: "MDET_EDIM", -3: "MDET_EPOPCOUNT",
+          -4: "MDET_EORBITAL", -5: "MDET_EDUPLICATE", -6: "MDET_ESPIN", -7: "MDET_ENOMEM",
+          -8: "MDET_EHIP", -9: "MDET_ESTATE", -10: "MDET_EDEGREE"}
+
+# every symbol include/mdet.h declares (checked by the CPU tests)
+EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbitals",
+            "mdet_set_expansion", "mdet_get_indexing", "mdet_eval_walkers",
+            "mdet_set_fallback_threshold", "mdet_get_stats", "mdet_set_profiling",
+            "mdet_get_kernel_times"]
+
+
+class MdetError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_det", ctypes.c_int64), ("n_uniq_up", ctypes.c_int64),
+                ("n_uniq_dn", ctypes.c_int64), ("n_up", ctypes.c_int32),
+                ("n_dn", ctypes.c_int32), ("n_mo", ctypes.c_int32), ("n_prim", ctypes.c_int32),
+                ("n_int", ctypes.c_int32), ("ref_up", ctypes.c_int64), ("ref_dn", ctypes.c_int64),
+                ("n_by_degree_up", ctypes.c_int64 * (MAX_DEGREE + 1)),
+                ("n_by_degree_dn", ctypes.c_int64 * (MAX_DEGREE + 1)),
+                ("workspace_bytes", ctypes.c_int64), ("expansion_bytes", ctypes.c_int64),
+                ("preprocess_seconds", ctypes.c_double)]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(f"libmdet.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "mdet_create": (I32, [ctypes.POINTER(P), I32]),
+        "mdet_destroy": (None, [P]),
+        "mdet_last_error": (ctypes.c_char_p, [P]),
+        "mdet_init_orbitals": (I32, [P, I32, I32, P, P, P]),
+        "mdet_set_expansion": (I32, [P, I32, I32, I32, I64, P, P, P]),
+        "mdet_get_indexing": (I32, [P, P, P, P, P, P, P, P, P, P, P]),
+        "mdet_eval_walkers": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
+        "mdet_set_fallback_threshold": (I32, [P, D]),
+        "mdet_get_stats": (I32, [P, P]),
+        "mdet_set_profiling": (I32, [P, I32]),
+        "mdet_get_kernel_times": (I32, [P, I32, P, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    return lib
+
+
+_LIB = load_library()
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _dptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Evaluator:
+    """One libmdet context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        rc = _LIB.mdet_create(ctypes.byref(h), int(device))
+        if rc != 0:
+            raise MdetError(rc, f"mdet_create(device={device}) failed")
+        self._h = h
+        self.device = device
+        self.n_up = self.n_dn = self.n_mo = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _LIB.mdet_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != 0:
+            raise MdetError(rc, _LIB.mdet_last_error(self._h).decode())
+
+    # -------------------------------------------------------------- setup
+    def init_orbitals(self, pow_abc, alpha, coef):
+        pw = np.ascontiguousarray(pow_abc, dtype=np.int32)
+        al = np.ascontiguousarray(alpha, dtype=np.float64)
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        n_mo, n_prim = al.shape
+        self._check(_LIB.mdet_init_orbitals(self._h, n_mo, n_prim, _ptr(pw), _ptr(al), _ptr(cf)))
+        self.n_mo = n_mo
+
+    def set_expansion(self, n_up, n_dn, det_up, det_dn, c, n_int=None):
+        du = np.ascontiguousarray(det_up, dtype=np.uint64)
+        dd = np.ascontiguousarray(det_dn, dtype=np.uint64)
+        cc = np.ascontiguousarray(c, dtype=np.float64)
+        if du.ndim == 1:
+            du = du.reshape(-1, 1)
+            dd = dd.reshape(-1, 1)
+        n_int = du.shape[1] if n_int is None else n_int
+        self._check(_LIB.mdet_set_expansion(self._h, int(n_up), int(n_dn), int(n_int),
+                                            int(cc.shape[0]), _ptr(du), _ptr(dd), _ptr(cc)))
+        self.n_up, self.n_dn = int(n_up), int(n_dn)
+
+    def load_workload(self, wl):
+        self.init_orbitals(wl.pow_abc, wl.alpha, wl.coef)
+        self.set_expansion(wl.n_up, wl.n_dn, wl.det_up, wl.det_dn, wl.c, wl.n_int)
+
+    def set_fallback_threshold(self, kappa_max: float):
+        self._check(_LIB.mdet_set_fallback_threshold(self._h, float(kappa_max)))
+
+    def indexing(self):
+        nu = ctypes.c_int64()
+        nd = ctypes.c_int64()
+        self._check(_LIB.mdet_get_indexing(self._h, ctypes.byref(nu), ctypes.byref(nd),
+                                           None, None, None, None, None, None, None, None))
+        st = self.stats()
+        n_int, Z = st.n_int, st.n_det
+        out = dict(uniq_up=np.zeros((nu.value, n_int), np.uint64),
+                   uniq_dn=np.zeros((nd.value, n_int), np.uint64),
+                   row_i=np.zeros(Z, np.int32), col_j=np.zeros(Z, np.int32),
+                   val=np.zeros(Z, np.float64), src_pos=np.zeros(Z, np.int64))
+        ru, rd = ctypes.c_int64(), ctypes.c_int64()
+        self._check(_LIB.mdet_get_indexing(self._h, None, None, _ptr(out["uniq_up"]),
+                                           _ptr(out["uniq_dn"]), _ptr(out["row_i"]),
+                                           _ptr(out["col_j"]), _ptr(out["val"]),
+                                           _ptr(out["src_pos"]), ctypes.byref(ru),
+                                           ctypes.byref(rd)))
+        out["ref_up"], out["ref_dn"] = ru.value, rd.value
+        return out
+
+    def set_profiling(self, enable: bool):
+        self._check(_LIB.mdet_set_profiling(self._h, 1 if enable else 0))
+
+    def kernel_times(self):
+        """{kernel name: total ms} over the profiled calls, and the call count."""
+        cap = 32
+        ms = np.zeros(cap)
+        names = (ctypes.c_char_p * cap)()
+        nk = ctypes.c_int32()
+        nc = ctypes.c_int64()
+        self._check(_LIB.mdet_get_kernel_times(self._h, cap, _ptr(ms), ctypes.cast(names, ctypes.c_void_p),
+                                               ctypes.byref(nk), ctypes.byref(nc)))
+        return {names[k].decode(): float(ms[k]) for k in range(nk.value)}, nc.value
+
+    def stats(self) -> Stats:
+        s = Stats()
+        self._check(_LIB.mdet_get_stats(self._h, ctypes.byref(s)))
+        return s
+
+    # -------------------------------------------------------------- hot path
+    def eval_raw(self, n_walk, R_ptr, precision, maxdeg_ptr, sign_ptr, logabs_ptr, gl_ptr,
+                 wstatus_ptr, stream_ptr):
+        """Direct call with raw device pointers (ints or c_void_p)."""
+        self._check(_LIB.mdet_eval_walkers(self._h, int(n_walk), R_ptr, int(precision),
+                                           maxdeg_ptr, sign_ptr, logabs_ptr, gl_ptr,
+                                           wstatus_ptr, stream_ptr))
+
+    def eval_walkers(self, R, precision=MDET_FP64, max_degree=None, out=None, stream=None):
+        """R: torch float64 [W][N][3] on this device.  Returns (sign, logabs, gl, wstatus)
+        torch tensors on the device; the call is asynchronous on ``stream``
+        (default: torch's current stream)."""
+        import torch
+        if not (R.is_cuda and R.dtype == torch.float64 and R.is_contiguous()):
+            raise ValueError("R must be a contiguous float64 tensor on the GPU")
+        W, N = R.shape[0], R.shape[1]
+        if N != self.n_up + self.n_dn or R.shape[2] != 3:
+            raise ValueError("R must have shape [W][n_up+n_dn][3]")
+        if max_degree is not None and not (max_degree.is_cuda and max_degree.dtype == torch.int8
+                                           and max_degree.shape == (W,)):
+            raise ValueError("max_degree must be an int8 [W] tensor on the GPU")
+        if out is None:
+            out = (torch.empty(W, dtype=torch.float64, device=R.device),
+                   torch.empty(W, dtype=torch.float64, device=R.device),
+                   torch.empty((W, N, 4), dtype=torch.float64, device=R.device),
+                   torch.empty(W, dtype=torch.int32, device=R.device))
+        sign, logabs, gl, ws = out
+        if stream is None:
+            stream = torch.cuda.current_stream(R.device)
+        self.eval_raw(W, _dptr(R), precision, _dptr(max_degree), _dptr(sign), _dptr(logabs),
+                      _dptr(gl), _dptr(ws), ctypes.c_void_p(stream.cuda_stream))
+        return out

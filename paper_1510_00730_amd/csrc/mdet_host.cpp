@@ -1,0 +1,736 @@
+// Host side of libmdet: context, the one-time pre-processing of the CI
+// expansion (Sec. 2.1), the excitation analysis against the reference
+// determinant, device upload, and the C ABI declared in include/mdet.h.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "mdet_internal.h"
+
+using namespace mdet;
+
+namespace {
+
+struct Status : std::runtime_error {
+    mdet_status code;
+    Status(mdet_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_OK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess)                                                          \
+            throw Status(_e == hipErrorOutOfMemory ? MDET_ENOMEM : MDET_EHIP,          \
+                         std::string(#expr) + ": " + hipGetErrorString(_e));           \
+    } while (0)
+
+// A device allocation owned by the context.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t n) {
+        release();
+        if (n == 0) n = 64;
+        HIP_OK(hipMalloc(&p, n));
+        bytes = n;
+    }
+    template <typename T>
+    void upload(const std::vector<T> &v) {
+        alloc(sizeof(T) * v.size());
+        if (!v.empty()) HIP_OK(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+struct SpinHost {
+    int n = 0;
+    int64_t U = 0;
+    std::vector<uint64_t> uniq;      // [U][n_int], public (omega) order
+    int64_t ref = 0;                 // public index of the reference
+    std::vector<int32_t> occ0;       // [n]
+    std::vector<int32_t> exec_of;    // public -> exec
+    std::vector<int32_t> pub_of;     // exec -> public
+    std::vector<DetDesc> desc;       // exec order
+    int64_t n_by_degree[MDET_MAX_DEGREE + 1] = {0};
+    std::vector<int32_t> gptr;
+    std::vector<uint32_t> gent;
+    DevBuf d_occ0, d_desc, d_gptr, d_gent;
+};
+
+}  // namespace
+
+struct mdet_ctx {
+    int device = 0;
+    bool host_only = false;  // created with hip_device == -1: pre-processing only
+    std::string err;
+    // orbitals
+    bool have_orb = false;
+    int n_mo = 0, n_prim = 0;
+    std::vector<Prim> prim;
+    DevBuf d_prim;
+    // expansion
+    bool have_exp = false;
+    int n_up = 0, n_dn = 0, n_int = 0;
+    int64_t n_det = 0;
+    SpinHost sp[2];
+    std::vector<int32_t> row_i, col_j;
+    std::vector<double> val;
+    std::vector<int64_t> src_pos;
+    DevBuf d_rptr, d_rcol, d_rval, d_rval32, d_cptr, d_crow, d_cval, d_cval32;
+    double prep_seconds = 0.0;
+    double kappa_max = 3e4;
+    // optional per-kernel timing with HIP events on the caller's stream: a
+    // ring of event sets, harvested when the ring wraps or on request
+    static constexpr int kRing = 64;
+    bool profiling = false;
+    std::vector<hipEvent_t> prof_ev;  // [kRing][kNumKernels + 1]
+    int prof_head = 0, prof_pending = 0;
+    double prof_ms[kNumKernels] = {0};
+    int64_t prof_calls = 0;
+    void harvest_one() {  // oldest pending set
+        const int slot = (prof_head - prof_pending + kRing) % kRing;
+        hipEvent_t *e = &prof_ev[(size_t)slot * (kNumKernels + 1)];
+        (void)hipEventSynchronize(e[kNumKernels]);
+        for (int k = 0; k < kNumKernels; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e[k], e[k + 1]) == hipSuccess) prof_ms[k] += ms;
+        }
+        ++prof_calls;
+        --prof_pending;
+    }
+    void harvest_all() {
+        while (prof_pending > 0) harvest_one();
+    }
+    hipEvent_t *next_event_set() {
+        if (prof_pending == kRing) harvest_one();
+        hipEvent_t *e = &prof_ev[(size_t)prof_head * (kNumKernels + 1)];
+        prof_head = (prof_head + 1) % kRing;
+        ++prof_pending;
+        return e;
+    }
+    void drop_profile_events() {
+        for (auto &e : prof_ev)
+            if (e) (void)hipEventDestroy(e);
+        prof_ev.clear();
+        prof_pending = 0;
+        prof_head = 0;
+    }
+    // walker work buffers
+    int64_t wcap = 0;
+    DevBuf w_phi, w_E, w_X, w_T, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
+        w_uv32, w_psi64, w_psi32;
+    Work wk{};
+
+    void drop_expansion() {
+        have_exp = false;
+        for (auto &s : sp) {
+            s.d_occ0.release();
+            s.d_desc.release();
+            s.d_gptr.release();
+            s.d_gent.release();
+            s = SpinHost();
+        }
+        for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_cptr, &d_crow, &d_cval, &d_cval32})
+            b->release();
+        drop_work();
+    }
+    void drop_work() {
+        for (DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag, &w_K,
+                          &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_psi32})
+            b->release();
+        wcap = 0;
+    }
+    int64_t work_bytes() const {
+        int64_t t = 0;
+        for (const DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag,
+                                &w_K, &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_psi32})
+            t += (int64_t)b->bytes;
+        return t;
+    }
+    int64_t exp_bytes() const {
+        int64_t t = (int64_t)d_prim.bytes;
+        for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_cptr, &d_crow, &d_cval, &d_cval32})
+            t += (int64_t)b->bytes;
+        for (const auto &s : sp)
+            t += (int64_t)(s.d_occ0.bytes + s.d_desc.bytes + s.d_gptr.bytes + s.d_gent.bytes);
+        return t;
+    }
+};
+
+namespace {
+
+int popcount64(uint64_t x) { return __builtin_popcountll(x); }
+
+// Key of Eq. (comp) (xor of the words as unsigned), ties broken by the words
+// from the last to the first, unsigned.  Returns <0, 0, >0.
+int compare_dets(const uint64_t *x, const uint64_t *y, int n_int) {
+    uint64_t ox = 0, oy = 0;
+    for (int w = 0; w < n_int; ++w) {
+        ox ^= x[w];
+        oy ^= y[w];
+    }
+    if (ox != oy) return ox < oy ? -1 : 1;
+    for (int w = n_int - 1; w >= 0; --w)
+        if (x[w] != y[w]) return x[w] < y[w] ? -1 : 1;
+    return 0;
+}
+
+std::vector<int32_t> occupied(const uint64_t *d, int n_int) {
+    std::vector<int32_t> o;
+    for (int w = 0; w < n_int; ++w) {
+        uint64_t x = d[w];
+        while (x) {
+            const int b = __builtin_ctzll(x);
+            o.push_back(64 * w + b);
+            x &= x - 1;
+        }
+    }
+    return o;
+}
+
+// Sort and deduplicate one spin list; pos[k] = distinct index of product k.
+void unique_spin_list(const uint64_t *dets, int64_t n_det, int n_int, SpinHost &s,
+                      std::vector<int32_t> &pos) {
+    std::vector<int64_t> order(n_det);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+        const int c = compare_dets(dets + a * n_int, dets + b * n_int, n_int);
+        return c < 0 || (c == 0 && a < b);
+    });
+    pos.assign(n_det, -1);
+    s.uniq.clear();
+    int64_t U = 0;
+    for (int64_t t = 0; t < n_det; ++t) {
+        const uint64_t *d = dets + order[t] * n_int;
+        if (U == 0 || compare_dets(s.uniq.data() + (U - 1) * n_int, d, n_int) != 0) {
+            s.uniq.insert(s.uniq.end(), d, d + n_int);
+            ++U;
+        }
+        pos[order[t]] = (int32_t)(U - 1);
+    }
+    s.U = U;
+}
+
+void validate_spin(const SpinHost &s, int n_int, int n_mo, const char *name) {
+    for (int64_t i = 0; i < s.U; ++i) {
+        const uint64_t *d = s.uniq.data() + i * n_int;
+        int pc = 0;
+        for (int w = 0; w < n_int; ++w) pc += popcount64(d[w]);
+        if (pc != s.n)
+            throw Status(MDET_EPOPCOUNT, std::string(name) + " determinant with " +
+                                             std::to_string(pc) + " set bits, expected " +
+                                             std::to_string(s.n));
+        for (int w = 0; w < n_int; ++w) {
+            const int lo = 64 * w;
+            if (d[w] == 0) continue;
+            const int hi = lo + 63 - __builtin_clzll(d[w]);
+            if (hi >= n_mo)
+                throw Status(MDET_EORBITAL, std::string(name) + " determinant occupies orbital " +
+                                                std::to_string(hi) + " >= n_mo");
+        }
+    }
+}
+
+// Excitation analysis relative to the reference, execution order by degree,
+// and the lists that aggregate adjugate entries per (slot, orbital) target.
+void analyse_spin(SpinHost &s, int n_int, int n_mo) {
+    const uint64_t *ref = s.uniq.data() + s.ref * n_int;
+    s.occ0 = occupied(ref, n_int);
+    const int n = s.n;
+    std::vector<DetDesc> pub_desc(s.U);
+    std::vector<int> deg(s.U);
+    std::vector<int32_t> slot_of(n_mo, -1);
+    for (int c = 0; c < n; ++c) slot_of[s.occ0[c]] = c;
+    for (int64_t i = 0; i < s.U; ++i) {
+        const uint64_t *d = s.uniq.data() + i * n_int;
+        DetDesc D;
+        std::memset(&D, 0, sizeof(D));
+        int nh = 0, np = 0;
+        for (int c = 0; c < n; ++c) {
+            const int m = s.occ0[c];
+            if (!((d[m >> 6] >> (m & 63)) & 1ull)) {
+                if (nh >= MDET_MAX_DEGREE)
+                    throw Status(MDET_EDEGREE, "excitation degree above " +
+                                                   std::to_string(MDET_MAX_DEGREE));
+                D.h[nh++] = (uint8_t)c;
+            }
+        }
+        for (int32_t m : occupied(d, n_int)) {
+            if (slot_of[m] < 0) {
+                if (np >= MDET_MAX_DEGREE)
+                    throw Status(MDET_EDEGREE, "excitation degree above " +
+                                                   std::to_string(MDET_MAX_DEGREE));
+                D.p[np++] = (uint16_t)m;
+            }
+        }
+        D.s = (uint8_t)nh;
+        // sign of the permutation sorting occ0 with h[a] -> p[a] substituted in place
+        std::vector<int32_t> lst(s.occ0);
+        for (int a = 0; a < nh; ++a) lst[D.h[a]] = D.p[a];
+        int inv = 0;
+        for (int x = 0; x < n; ++x)
+            for (int y = x + 1; y < n; ++y) inv += lst[x] > lst[y];
+        D.eps = (inv & 1) ? -1 : 1;
+        pub_desc[i] = D;
+        deg[i] = nh;
+    }
+    s.pub_of.resize(s.U);
+    std::iota(s.pub_of.begin(), s.pub_of.end(), 0);
+    std::stable_sort(s.pub_of.begin(), s.pub_of.end(),
+                     [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+    s.exec_of.assign(s.U, 0);
+    s.desc.resize(s.U);
+    for (int k = 0; k <= MDET_MAX_DEGREE; ++k) s.n_by_degree[k] = 0;
+    for (int64_t e = 0; e < s.U; ++e) {
+        s.exec_of[s.pub_of[e]] = (int32_t)e;
+        s.desc[e] = pub_desc[s.pub_of[e]];
+        s.n_by_degree[s.desc[e].s]++;
+    }
+    // aggregation lists: target t = h[a]*M + p[b] <- (d, a, b)
+    const int64_t nt = (int64_t)n * n_mo;
+    s.gptr.assign(nt + 1, 0);
+    for (int64_t e = 0; e < s.U; ++e) {
+        const DetDesc &D = s.desc[e];
+        for (int a = 0; a < D.s; ++a)
+            for (int b = 0; b < D.s; ++b) s.gptr[(int64_t)D.h[a] * n_mo + D.p[b] + 1]++;
+    }
+    for (int64_t t = 0; t < nt; ++t) s.gptr[t + 1] += s.gptr[t];
+    s.gent.assign(s.gptr[nt], 0);
+    std::vector<int32_t> fill(s.gptr.begin(), s.gptr.end() - 1);
+    for (int64_t e = 0; e < s.U; ++e) {
+        const DetDesc &D = s.desc[e];
+        for (int a = 0; a < D.s; ++a)
+            for (int b = 0; b < D.s; ++b) {
+                const int64_t t = (int64_t)D.h[a] * n_mo + D.p[b];
+                s.gent[fill[t]++] = ((uint32_t)e << 8) | ((uint32_t)a << 4) | (uint32_t)b;
+            }
+    }
+}
+
+template <typename Fn>
+mdet_status guarded(mdet_ctx *ctx, Fn &&fn) {
+    if (!ctx) return MDET_EINVAL;
+    try {
+        ctx->err.clear();
+        fn();
+        return MDET_OK;
+    } catch (const Status &s) {
+        ctx->err = s.what();
+        return s.code;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return MDET_ENOMEM;
+    } catch (const std::exception &e) {
+        ctx->err = e.what();
+        return MDET_EINVAL;
+    }
+}
+
+void require(bool cond, mdet_status code, const char *msg) {
+    if (!cond) throw Status(code, msg);
+}
+
+void ensure_work(mdet_ctx *c, int64_t W) {
+    if (W <= c->wcap) return;
+    c->drop_work();
+    const int M = c->n_mo, N = c->n_up + c->n_dn;
+    const int nmax = std::max(c->n_up, c->n_dn);
+    const int64_t Upad = (c->sp[0].U + 63) / 64 * 64, Vpad = (c->sp[1].U + 63) / 64 * 64;
+    const int64_t RV = Upad + Vpad;
+    c->w_phi.alloc(sizeof(double) * W * N * 5 * M);
+    c->w_E.alloc(sizeof(int32_t) * W * 2 * M);
+    c->w_X.alloc(sizeof(double) * W * 2 * nmax * nmax);
+    c->w_T.alloc(sizeof(double) * W * 2 * nmax * M);
+    c->w_g0.alloc(sizeof(double) * W * N * 4);
+    c->w_logdet0.alloc(sizeof(double) * W * 2);
+    c->w_sign0.alloc(sizeof(double) * W * 2);
+    c->w_flag.alloc(sizeof(int32_t) * W * 2);
+    c->w_K.alloc(sizeof(int32_t) * W * 2);
+    c->w_R64.alloc(sizeof(double) * W * RV);
+    c->w_R32.alloc(sizeof(float) * W * RV);
+    c->w_uv64.alloc(sizeof(double) * W * RV);
+    c->w_uv32.alloc(sizeof(float) * W * RV);
+    c->w_psi64.alloc(sizeof(double) * W);
+    c->w_psi32.alloc(sizeof(float) * W);
+    Work &k = c->wk;
+    k.W = W;
+    k.M = M;
+    k.N = N;
+    k.nmax = nmax;
+    k.Upad = (int32_t)Upad;
+    k.Vpad = (int32_t)Vpad;
+    k.phi = c->w_phi.as<double>();
+    k.E = c->w_E.as<int32_t>();
+    k.X = c->w_X.as<double>();
+    k.T = c->w_T.as<double>();
+    k.g0 = c->w_g0.as<double>();
+    k.logdet0 = c->w_logdet0.as<double>();
+    k.sign0 = c->w_sign0.as<double>();
+    k.flag = c->w_flag.as<int32_t>();
+    k.K = c->w_K.as<int32_t>();
+    k.R64 = c->w_R64.as<double>();
+    k.R32 = c->w_R32.as<float>();
+    k.uv64 = c->w_uv64.as<double>();
+    k.uv32 = c->w_uv32.as<float>();
+    k.psi64 = c->w_psi64.as<double>();
+    k.psi32 = c->w_psi32.as<float>();
+    c->wcap = W;
+}
+
+}  // namespace
+
+extern "C" {
+
+mdet_status mdet_create(mdet_ctx **out, int32_t hip_device) {
+    if (!out) return MDET_EINVAL;
+    *out = nullptr;
+    if (hip_device == -1) {
+        mdet_ctx *c = new (std::nothrow) mdet_ctx();
+        if (!c) return MDET_ENOMEM;
+        c->device = -1;
+        c->host_only = true;
+        *out = c;
+        return MDET_OK;
+    }
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device < 0 || hip_device >= count)
+        return MDET_EHIP;
+    if (hipSetDevice(hip_device) != hipSuccess) return MDET_EHIP;
+    mdet_ctx *c = new (std::nothrow) mdet_ctx();
+    if (!c) return MDET_ENOMEM;
+    c->device = hip_device;
+    *out = c;
+    return MDET_OK;
+}
+
+void mdet_destroy(mdet_ctx *ctx) {
+    if (!ctx) return;
+    if (!ctx->host_only) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    ctx->drop_expansion();
+    ctx->d_prim.release();
+    ctx->drop_profile_events();
+    delete ctx;
+}
+
+const char *mdet_last_error(const mdet_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim, const int32_t *pow_abc,
+                               const double *alpha, const double *coef) {
+    return guarded(ctx, [&] {
+        require(pow_abc && alpha && coef, MDET_EINVAL, "null orbital array");
+        require(n_mo >= 1 && n_mo <= MDET_MAX_MO, MDET_EDIM, "n_mo out of range");
+        require(n_prim >= 1 && n_prim <= 16, MDET_EDIM, "n_prim out of range");
+        std::vector<Prim> pr((size_t)n_mo * n_prim);
+        for (int64_t t = 0; t < (int64_t)n_mo * n_prim; ++t) {
+            Prim &p = pr[t];
+            p.alpha = alpha[t];
+            p.coef = coef[t];
+            p.a = pow_abc[3 * t];
+            p.b = pow_abc[3 * t + 1];
+            p.c = pow_abc[3 * t + 2];
+            p.pad = 0;
+            require(p.a >= 0 && p.a <= 4 && p.b >= 0 && p.b <= 4 && p.c >= 0 && p.c <= 4,
+                    MDET_EINVAL, "monomial power outside 0..4");
+            require(std::isfinite(p.alpha) && p.alpha > 0.0 && std::isfinite(p.coef), MDET_EINVAL,
+                    "exponents must be finite and positive, coefficients finite");
+        }
+        if (!ctx->host_only) HIP_OK(hipSetDevice(ctx->device));
+        ctx->drop_expansion();
+        if (!ctx->host_only) ctx->d_prim.upload(pr);
+        ctx->prim.swap(pr);
+        ctx->n_mo = n_mo;
+        ctx->n_prim = n_prim;
+        ctx->have_orb = true;
+    });
+}
+
+mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_t n_int,
+                               int64_t n_det, const uint64_t *det_up, const uint64_t *det_dn,
+                               const double *c) {
+    return guarded(ctx, [&] {
+        const auto t0 = std::chrono::steady_clock::now();
+        require(ctx->have_orb, MDET_ESTATE, "mdet_init_orbitals must come first");
+        require(det_up && det_dn && c, MDET_EINVAL, "null expansion array");
+        require(n_det >= 1 && n_det <= INT32_MAX, MDET_EDIM, "n_det out of range");
+        require(n_up >= n_dn, MDET_ESPIN, "n_up < n_dn: the up spin must hold the larger count");
+        require(n_dn >= 1 && n_up <= MDET_MAX_SPIN_ELEC, MDET_EDIM, "electron count out of range");
+        require(n_up <= ctx->n_mo, MDET_EDIM, "more electrons of one spin than orbitals");
+        require(n_int == (ctx->n_mo + 63) / 64, MDET_EORBITAL, "n_int must equal ceil(n_mo/64)");
+        for (int64_t k = 0; k < n_det; ++k)
+            require(std::isfinite(c[k]), MDET_EINVAL, "non-finite coefficient");
+        if (!ctx->host_only) HIP_OK(hipSetDevice(ctx->device));
+        ctx->drop_expansion();
+        SpinHost sp[2];
+        sp[0].n = n_up;
+        sp[1].n = n_dn;
+        std::vector<int32_t> pos_u, pos_d;
+        unique_spin_list(det_up, n_det, n_int, sp[0], pos_u);
+        unique_spin_list(det_dn, n_det, n_int, sp[1], pos_d);
+        validate_spin(sp[0], n_int, ctx->n_mo, "up");
+        validate_spin(sp[1], n_int, ctx->n_mo, "down");
+        const int64_t U = sp[0].U, V = sp[1].U;
+        // column-major coordinate order: key U*j + i
+        std::vector<int64_t> order(n_det);
+        std::iota(order.begin(), order.end(), 0);
+        std::vector<int64_t> key(n_det);
+        for (int64_t k = 0; k < n_det; ++k) key[k] = U * (int64_t)pos_d[k] + pos_u[k];
+        std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+            return key[a] < key[b] || (key[a] == key[b] && a < b);
+        });
+        for (int64_t t = 1; t < n_det; ++t)
+            if (key[order[t]] == key[order[t - 1]])
+                throw Status(MDET_EDUPLICATE, "product (det_up, det_dn) given twice, at positions " +
+                                                  std::to_string(order[t - 1]) + " and " +
+                                                  std::to_string(order[t]));
+        int64_t kref = 0;
+        for (int64_t k = 1; k < n_det; ++k)
+            if (std::fabs(c[k]) > std::fabs(c[kref])) kref = k;
+        sp[0].ref = pos_u[kref];
+        sp[1].ref = pos_d[kref];
+        analyse_spin(sp[0], n_int, ctx->n_mo);
+        analyse_spin(sp[1], n_int, ctx->n_mo);
+
+        std::vector<int32_t> row_i(n_det), col_j(n_det);
+        std::vector<double> val(n_det);
+        std::vector<int64_t> src(n_det);
+        for (int64_t t = 0; t < n_det; ++t) {
+            const int64_t k = order[t];
+            row_i[t] = pos_u[k];
+            col_j[t] = pos_d[k];
+            val[t] = c[k];
+            src[t] = k;
+        }
+        // sparse C in execution indices: CSR over up rows and CSC over down columns
+        std::vector<int32_t> rptr(U + 1, 0), cptr(V + 1, 0);
+        for (int64_t t = 0; t < n_det; ++t) {
+            rptr[sp[0].exec_of[row_i[t]] + 1]++;
+            cptr[sp[1].exec_of[col_j[t]] + 1]++;
+        }
+        for (int64_t i = 0; i < U; ++i) rptr[i + 1] += rptr[i];
+        for (int64_t j = 0; j < V; ++j) cptr[j + 1] += cptr[j];
+        std::vector<int32_t> rcol(n_det), crow(n_det);
+        std::vector<double> rval(n_det), cval(n_det);
+        {
+            std::vector<int32_t> fr(rptr.begin(), rptr.end() - 1), fc(cptr.begin(), cptr.end() - 1);
+            // visit entries in (exec col, exec row) order so both structures are sorted
+            std::vector<int64_t> ord(n_det);
+            std::iota(ord.begin(), ord.end(), 0);
+            std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+                const int64_t ja = sp[1].exec_of[col_j[a]], jb = sp[1].exec_of[col_j[b]];
+                if (ja != jb) return ja < jb;
+                return sp[0].exec_of[row_i[a]] < sp[0].exec_of[row_i[b]];
+            });
+            for (int64_t t : ord) {
+                const int32_t ie = sp[0].exec_of[row_i[t]], je = sp[1].exec_of[col_j[t]];
+                rcol[fr[ie]] = je;
+                rval[fr[ie]++] = val[t];
+                crow[fc[je]] = ie;
+                cval[fc[je]++] = val[t];
+            }
+        }
+        std::vector<float> rval32(rval.begin(), rval.end()), cval32(cval.begin(), cval.end());
+
+        for (int s = 0; s < 2 && !ctx->host_only; ++s) {
+            sp[s].d_occ0.upload(sp[s].occ0);
+            sp[s].d_desc.upload(sp[s].desc);
+            sp[s].d_gptr.upload(sp[s].gptr);
+            sp[s].d_gent.upload(sp[s].gent);
+        }
+        if (!ctx->host_only) {
+            ctx->d_rptr.upload(rptr);
+            ctx->d_rcol.upload(rcol);
+            ctx->d_rval.upload(rval);
+            ctx->d_rval32.upload(rval32);
+            ctx->d_cptr.upload(cptr);
+            ctx->d_crow.upload(crow);
+            ctx->d_cval.upload(cval);
+            ctx->d_cval32.upload(cval32);
+        }
+        for (int s = 0; s < 2; ++s) {
+            ctx->sp[s].n = sp[s].n;
+            ctx->sp[s].U = sp[s].U;
+            ctx->sp[s].uniq.swap(sp[s].uniq);
+            ctx->sp[s].ref = sp[s].ref;
+            ctx->sp[s].occ0.swap(sp[s].occ0);
+            ctx->sp[s].exec_of.swap(sp[s].exec_of);
+            ctx->sp[s].pub_of.swap(sp[s].pub_of);
+            ctx->sp[s].desc.swap(sp[s].desc);
+            for (int k = 0; k <= MDET_MAX_DEGREE; ++k) ctx->sp[s].n_by_degree[k] = sp[s].n_by_degree[k];
+            ctx->sp[s].gptr.swap(sp[s].gptr);
+            ctx->sp[s].gent.swap(sp[s].gent);
+            std::swap(ctx->sp[s].d_occ0, sp[s].d_occ0);
+            std::swap(ctx->sp[s].d_desc, sp[s].d_desc);
+            std::swap(ctx->sp[s].d_gptr, sp[s].d_gptr);
+            std::swap(ctx->sp[s].d_gent, sp[s].d_gent);
+        }
+        ctx->row_i.swap(row_i);
+        ctx->col_j.swap(col_j);
+        ctx->val.swap(val);
+        ctx->src_pos.swap(src);
+        ctx->n_up = n_up;
+        ctx->n_dn = n_dn;
+        ctx->n_int = n_int;
+        ctx->n_det = n_det;
+        ctx->have_exp = true;
+        ctx->prep_seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    });
+}
+
+mdet_status mdet_get_indexing(const mdet_ctx *cctx, int64_t *n_uniq_up, int64_t *n_uniq_dn,
+                              uint64_t *uniq_up, uint64_t *uniq_dn, int32_t *row_i, int32_t *col_j,
+                              double *val, int64_t *src_pos, int64_t *ref_up, int64_t *ref_dn) {
+    mdet_ctx *ctx = const_cast<mdet_ctx *>(cctx);
+    return guarded(ctx, [&] {
+        require(ctx->have_exp, MDET_ESTATE, "no expansion loaded");
+        if (n_uniq_up) *n_uniq_up = ctx->sp[0].U;
+        if (n_uniq_dn) *n_uniq_dn = ctx->sp[1].U;
+        if (uniq_up) std::memcpy(uniq_up, ctx->sp[0].uniq.data(), sizeof(uint64_t) * ctx->sp[0].uniq.size());
+        if (uniq_dn) std::memcpy(uniq_dn, ctx->sp[1].uniq.data(), sizeof(uint64_t) * ctx->sp[1].uniq.size());
+        if (row_i) std::memcpy(row_i, ctx->row_i.data(), sizeof(int32_t) * ctx->n_det);
+        if (col_j) std::memcpy(col_j, ctx->col_j.data(), sizeof(int32_t) * ctx->n_det);
+        if (val) std::memcpy(val, ctx->val.data(), sizeof(double) * ctx->n_det);
+        if (src_pos) std::memcpy(src_pos, ctx->src_pos.data(), sizeof(int64_t) * ctx->n_det);
+        if (ref_up) *ref_up = ctx->sp[0].ref;
+        if (ref_dn) *ref_dn = ctx->sp[1].ref;
+    });
+}
+
+mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
+                              const int8_t *max_degree_dev, double *sign_dev, double *logabs_dev,
+                              double *gl_dev, int32_t *wstatus_dev, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context (hip_device -1) cannot evaluate");
+        require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
+        require(n_walk >= 0 && n_walk <= (int64_t)1 << 30, MDET_EDIM, "n_walk out of range");
+        require(precision == MDET_FP64 || precision == MDET_MIXED, MDET_EINVAL, "unknown precision");
+        if (n_walk == 0) return;
+        require(R_dev && sign_dev && logabs_dev && gl_dev, MDET_EINVAL, "null output pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        ensure_work(ctx, n_walk);
+        KernelArgs a{};
+        a.n_up = ctx->n_up;
+        a.n_dn = ctx->n_dn;
+        a.N = ctx->n_up + ctx->n_dn;
+        a.M = ctx->n_mo;
+        a.P = ctx->n_prim;
+        a.nmax = std::max(ctx->n_up, ctx->n_dn);
+        a.kappa_max = ctx->kappa_max;
+        a.prim = ctx->d_prim.as<Prim>();
+        for (int s = 0; s < 2; ++s) {
+            SpinDev &d = a.sp[s];
+            d.n = ctx->sp[s].n;
+            d.e0 = s == 0 ? 0 : ctx->n_up;
+            d.U = (int32_t)ctx->sp[s].U;
+            d.occ0 = ctx->sp[s].d_occ0.as<int32_t>();
+            d.desc = ctx->sp[s].d_desc.as<DetDesc>();
+            d.gptr = ctx->sp[s].d_gptr.as<int32_t>();
+            d.gent = ctx->sp[s].d_gent.as<uint32_t>();
+        }
+        a.C.U = (int32_t)ctx->sp[0].U;
+        a.C.V = (int32_t)ctx->sp[1].U;
+        a.C.Z = ctx->n_det;
+        a.C.rptr = ctx->d_rptr.as<int32_t>();
+        a.C.rcol = ctx->d_rcol.as<int32_t>();
+        a.C.rval = ctx->d_rval.as<double>();
+        a.C.rval32 = ctx->d_rval32.as<float>();
+        a.C.cptr = ctx->d_cptr.as<int32_t>();
+        a.C.crow = ctx->d_crow.as<int32_t>();
+        a.C.cval = ctx->d_cval.as<double>();
+        a.C.cval32 = ctx->d_cval32.as<float>();
+        a.wk = ctx->wk;
+        a.W = n_walk;
+        a.R = R_dev;
+        a.max_degree = max_degree_dev;
+        a.precision = precision;
+        a.sign_out = sign_dev;
+        a.logabs_out = logabs_dev;
+        a.gl_out = gl_dev;
+        a.wstatus = wstatus_dev;
+        hipEvent_t *ev = ctx->profiling ? ctx->next_event_set() : nullptr;
+        HIP_OK(launch_eval(a, static_cast<hipStream_t>(hip_stream), ev));
+    });
+}
+
+mdet_status mdet_set_profiling(mdet_ctx *ctx, int32_t enable) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        HIP_OK(hipSetDevice(ctx->device));
+        ctx->harvest_all();
+        if (enable && ctx->prof_ev.empty()) {
+            ctx->prof_ev.assign((size_t)mdet_ctx::kRing * (kNumKernels + 1), nullptr);
+            for (auto &e : ctx->prof_ev) HIP_OK(hipEventCreate(&e));
+        }
+        ctx->profiling = enable != 0;
+        for (double &m : ctx->prof_ms) m = 0.0;
+        ctx->prof_calls = 0;
+    });
+}
+
+mdet_status mdet_get_kernel_times(mdet_ctx *ctx, int32_t capacity, double *ms_total,
+                                  const char **names, int32_t *n_kernels, int64_t *n_calls) {
+    return guarded(ctx, [&] {
+        ctx->harvest_all();
+        if (n_kernels) *n_kernels = kNumKernels;
+        if (n_calls) *n_calls = ctx->prof_calls;
+        for (int k = 0; k < kNumKernels && k < capacity; ++k) {
+            if (ms_total) ms_total[k] = ctx->prof_ms[k];
+            if (names) names[k] = kernel_name(k);
+        }
+    });
+}
+
+mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, double kappa_max) {
+    return guarded(ctx, [&] {
+        require(kappa_max > 0.0, MDET_EINVAL, "threshold must be positive");
+        ctx->kappa_max = kappa_max;
+    });
+}
+
+mdet_status mdet_get_stats(const mdet_ctx *cctx, mdet_stats *out) {
+    mdet_ctx *ctx = const_cast<mdet_ctx *>(cctx);
+    return guarded(ctx, [&] {
+        require(out != nullptr, MDET_EINVAL, "null stats pointer");
+        std::memset(out, 0, sizeof(*out));
+        out->n_mo = ctx->n_mo;
+        out->n_prim = ctx->n_prim;
+        if (ctx->have_exp) {
+            out->n_det = ctx->n_det;
+            out->n_uniq_up = ctx->sp[0].U;
+            out->n_uniq_dn = ctx->sp[1].U;
+            out->n_up = ctx->n_up;
+            out->n_dn = ctx->n_dn;
+            out->n_int = ctx->n_int;
+            out->ref_up = ctx->sp[0].ref;
+            out->ref_dn = ctx->sp[1].ref;
+            for (int k = 0; k <= MDET_MAX_DEGREE; ++k) {
+                out->n_by_degree_up[k] = ctx->sp[0].n_by_degree[k];
+                out->n_by_degree_dn[k] = ctx->sp[1].n_by_degree[k];
+            }
+        }
+        out->workspace_bytes = ctx->work_bytes();
+        out->expansion_bytes = ctx->exp_bytes();
+        out->preprocess_seconds = ctx->prep_seconds;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, on the
+benchmark workloads and on edge cases.  Scaled error bar: 1e-10 in FP64 mode,
+1e-5 in mixed mode (each output's error divided by the oracle's sum of the
+absolute values of the terms it adds up)."""
+import numpy as np
+import pytest
+
+import oracle
+from gen.workloads import encode, make_config, make_custom
+from parity_util import (FP64_TOL, MIXED_TOL, gpu_eval, log, rel_errors, scaled_errors,
+                         summary)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_1510_00730_amd as mdet  # noqa: E402
+
+_WL = {}
+_REF = {}
+
+
+def workload(cid):
+    if cid not in _WL:
+        _WL[cid] = make_config(cid)
+    return _WL[cid]
+
+
+def oracle_ref(cid, rows=None):
+    key = (cid, None if rows is None else tuple(rows))
+    if key not in _REF:
+        wl = workload(cid)
+        R = wl.R if rows is None else wl.R[list(rows)]
+        md = None if wl.max_degree is None else (wl.max_degree if rows is None else wl.max_degree[list(rows)])
+        _REF[key] = oracle.evaluate(wl, R, max_degree=md, n_threads=16)
+    return _REF[key]
+
+
+def evaluator(wl):
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    return ev
+
+
+@pytest.mark.parametrize("cid", [1, 2, 3])
+def test_fp64_parity_full_batch(cid):
+    log(f"[parity] config {cid} FP64 full batch")
+    wl = workload(cid)
+    ev = evaluator(wl)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=mdet.MDET_FP64)
+    ref = oracle_ref(cid)
+    ep, eg = scaled_errors(ref, sign, logabs, gl)
+    summary(f"c{cid} fp64", ep, eg, ws)
+    assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
+
+
+def test_mixed_parity_c3():
+    log("[parity] config 3 mixed")
+    wl = workload(3)
+    ev = evaluator(wl)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=mdet.MDET_MIXED)
+    ref = oracle_ref(3)
+    ep, eg = scaled_errors(ref, sign, logabs, gl)
+    summary("c3 mixed", ep, eg, ws)
+    rel = rel_errors(ref, gl)
+    log(f"c3 mixed plain relative grad/lap error p50 {np.median(rel):.2e} "
+        f"p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
+    assert ep.max() <= MIXED_TOL and eg.max() <= MIXED_TOL
+
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_uneven_batch_c4_sampled(precision, tol):
+    log(f"[parity] config 4 uneven, precision {precision}")
+    wl = workload(4)
+    ev = evaluator(wl)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=precision, max_degree=wl.max_degree)
+    rows = list(range(0, wl.n_walk, wl.n_walk // 48))
+    ref = oracle_ref(4, rows)
+    ep, eg = scaled_errors(ref, sign, logabs, gl, idx=rows)
+    summary(f"c4 prec{precision} sampled", ep, eg, ws[rows])
+    assert ep.max() <= tol and eg.max() <= tol
+
+
+def test_ragged_batches_and_reuse():
+    wl = workload(2)
+    ev = evaluator(wl)
+    ref = oracle_ref(2)
+    for W in (1, 333, 64, 256):
+        log(f"[parity] config 2 W={W}")
+        sign, logabs, gl, ws = gpu_eval(ev, wl.R[:W])
+        ep, eg = scaled_errors(oracle.evaluate(wl, wl.R[:W], n_threads=16), sign, logabs, gl) \
+            if W > 256 else scaled_errors(_sub(ref, W), sign, logabs, gl)
+        assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
+
+
+def _sub(ref, W):
+    return oracle.Result(ref.sign[:W], ref.logabs[:W], ref.gl[:W], ref.rs_psi[:W], ref.rs_gl[:W])
+
+
+def test_fp64_bitwise_deterministic():
+    log("[parity] determinism config 3")
+    wl = workload(3)
+    ev = evaluator(wl)
+    a = gpu_eval(ev, wl.R)
+    b = gpu_eval(ev, wl.R)
+    for x, y in zip(a, b):
+        assert x.tobytes() == y.tobytes()
+
+
+def test_forced_fallback_path():
+    """Every (walker, spin) through the direct-LU fallback."""
+    log("[parity] forced fallback config 2")
+    wl = workload(2)
+    ev = evaluator(wl)
+    ev.set_fallback_threshold(1e-300)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R[:64])
+    assert np.all(ws == mdet.W_FALLBACK)
+    ep, eg = scaled_errors(_sub(oracle_ref(2), 64), sign, logabs, gl)
+    summary("c2 forced fallback", ep, eg)
+    assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R[:64], precision=mdet.MDET_MIXED)
+    ep, eg = scaled_errors(_sub(oracle_ref(2), 64), sign, logabs, gl)
+    assert ep.max() <= MIXED_TOL and eg.max() <= MIXED_TOL
+
+
+def test_node_origin_and_tiny_config():
+    log("[parity] nodes and origin, config 1")
+    wl = workload(1)
+    ev = evaluator(wl)
+    R = wl.R.copy()
+    R[0, 1] = R[0, 0]          # coincident up electrons -> Psi = 0
+    R[1, 7] = R[1, 5]          # coincident down electrons -> Psi = 0
+    R[2, 3] = 0.0              # electron at the nucleus
+    R[3, 6, 0] = 0.0           # electron on a coordinate plane
+    sign, logabs, gl, ws = gpu_eval(ev, R)
+    assert ws[0] == mdet.W_NODE and ws[1] == mdet.W_NODE
+    assert sign[0] == 0 and logabs[0] == -np.inf and np.all(gl[0] == 0)
+    ref = oracle.evaluate(wl, R, n_threads=8)
+    ep, eg = scaled_errors(ref, sign, logabs, gl)
+    assert ep[2:].max() <= FP64_TOL and eg[2:].max() <= FP64_TOL
+
+
+def test_cauchy_binet_full_ci_on_gpu():
+    """Full-CI expansion with c_IJ = det B_up[I] det B_dn[J]: Psi factorises."""
+    import itertools
+    log("[parity] Cauchy-Binet full CI 8 orbitals 4+3")
+    n_mo, n_up, n_dn, W = 8, 4, 3, 64
+    wl = make_custom(n_up, n_dn, n_mo, 3, 2, 2, (1,), 1, W, sigma=1.0, seed=5,
+                     alpha_range=(0.2, 2.0))
+    rng = np.random.default_rng(5)
+    Bu, Bd = rng.normal(size=(n_mo, n_up)), rng.normal(size=(n_mo, n_dn))
+    I_all = list(itertools.combinations(range(n_mo), n_up))
+    J_all = list(itertools.combinations(range(n_mo), n_dn))
+    du = np.array([np.linalg.det(Bu[list(I)]) for I in I_all])
+    dd = np.array([np.linalg.det(Bd[list(J)]) for J in J_all])
+    ii, jj = np.meshgrid(np.arange(len(I_all)), np.arange(len(J_all)), indexing="ij")
+    ii, jj = ii.ravel(), jj.ravel()
+    wl.det_up = encode(I_all, 1)[ii]
+    wl.det_dn = encode(J_all, 1)[jj]
+    wl.c = du[ii] * dd[jj]
+    ev = evaluator(wl)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R)
+    for w in range(W):
+        orb = np.array([oracle.orbitals(wl, wl.R[w, e]) for e in range(wl.n_elec)])
+        s_tot, l_tot, g = 1.0, 0.0, np.zeros((wl.n_elec, 4))
+        for e0, n, B in ((0, n_up, Bu), (n_up, n_dn, Bd)):
+            P = orb[e0:e0 + n, 0] @ B
+            s, l = np.linalg.slogdet(P)
+            s_tot *= s
+            l_tot += l
+            Pi = np.linalg.inv(P)
+            for q in range(4):
+                g[e0:e0 + n, q] = np.einsum("ce,ec->e", Pi, orb[e0:e0 + n, 1 + q] @ B)
+        assert sign[w] == s_tot
+        assert abs(logabs[w] - l_tot) < 1e-9
+        assert np.abs(gl[w] - g).max() < 1e-8 * (1 + np.abs(g).max())
+
+
+def test_indexing_on_device_context_matches_oracle():
+    from oracle import preprocess as pp
+    wl = workload(3)
+    ev = evaluator(wl)
+    got = ev.indexing()
+    ref = pp.index_expansion(wl.det_up, wl.det_dn, wl.c)
+    for k in ("uniq_up", "uniq_dn", "row_i", "col_j", "src_pos"):
+        assert np.array_equal(got[k], ref[k]), k
