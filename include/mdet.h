@@ -58,7 +58,7 @@ enum { MDET_FP64 = 0, MDET_MIXED = 1 };
  * to the reference spin determinant that set_expansion accepts. */
 #define MDET_MAX_DEGREE 4
 /* Largest number of electrons of one spin. */
-#define MDET_MAX_SPIN_ELEC 32
+#define MDET_MAX_SPIN_ELEC 16
 /* Largest number of orbitals. */
 #define MDET_MAX_MO 512
 
@@ -106,7 +106,8 @@ mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim,
  * det_up, det_dn: uint64 [n_det][n_int] host; c: double [n_det] host.
  * Requires mdet_init_orbitals first.  Errors: MDET_ESPIN, MDET_EORBITAL,
  * MDET_EPOPCOUNT, MDET_EDUPLICATE, MDET_EDEGREE, MDET_EDIM (n_dn < 1,
- * n_up > MDET_MAX_SPIN_ELEC, n_up > n_mo, or n_det outside 1..2^31-1).
+ * n_up > MDET_MAX_SPIN_ELEC, n_up > n_mo, n_up * n_mo > 8192, or n_det
+ * outside 1..2^30-1).
  * Synchronous.
  */
 mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_t n_int,

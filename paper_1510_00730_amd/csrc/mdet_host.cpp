@@ -68,9 +68,9 @@ struct SpinHost {
     std::vector<int32_t> pub_of;     // exec -> public
     std::vector<DetDesc> desc;       // exec order
     int64_t n_by_degree[MDET_MAX_DEGREE + 1] = {0};
-    std::vector<int32_t> gptr;
-    std::vector<uint32_t> gent;
-    DevBuf d_occ0, d_desc, d_gptr, d_gent;
+    std::vector<int32_t> adj_off, chunk_det, gptr;
+    std::vector<uint16_t> gpos;
+    DevBuf d_occ0, d_desc, d_adj_off, d_chunk_det, d_gptr, d_gpos;
 };
 
 }  // namespace
@@ -92,7 +92,9 @@ struct mdet_ctx {
     std::vector<int32_t> row_i, col_j;
     std::vector<double> val;
     std::vector<int64_t> src_pos;
-    DevBuf d_rptr, d_rcol, d_rval, d_rval32, d_cptr, d_crow, d_cval, d_cval32;
+    DevBuf d_rptr, d_rcol, d_rval, d_rval32, d_rseg, d_cptr, d_crow, d_cval, d_cval32, d_cseg;
+    DevBuf d_rseg32, d_cseg32;
+    int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
     double prep_seconds = 0.0;
     double kappa_max = 3e4;
     // optional per-kernel timing with HIP events on the caller's stream: a
@@ -134,7 +136,7 @@ struct mdet_ctx {
     // walker work buffers
     int64_t wcap = 0;
     DevBuf w_phi, w_E, w_X, w_T, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
-        w_uv32, w_psi64, w_psi32;
+        w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart;
     Work wk{};
 
     void drop_expansion() {
@@ -142,33 +144,39 @@ struct mdet_ctx {
         for (auto &s : sp) {
             s.d_occ0.release();
             s.d_desc.release();
+            s.d_adj_off.release();
+            s.d_chunk_det.release();
             s.d_gptr.release();
-            s.d_gent.release();
+            s.d_gpos.release();
             s = SpinHost();
         }
-        for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_cptr, &d_crow, &d_cval, &d_cval32})
+        for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_rseg, &d_cptr, &d_crow, &d_cval,
+                          &d_cval32, &d_cseg, &d_rseg32, &d_cseg32})
             b->release();
         drop_work();
     }
     void drop_work() {
         for (DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag, &w_K,
-                          &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_psi32})
+                          &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp, &w_Kmax, &w_dpart})
             b->release();
         wcap = 0;
     }
     int64_t work_bytes() const {
         int64_t t = 0;
         for (const DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag,
-                                &w_K, &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_psi32})
+                                &w_K, &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp,
+                                &w_Kmax, &w_dpart})
             t += (int64_t)b->bytes;
         return t;
     }
     int64_t exp_bytes() const {
         int64_t t = (int64_t)d_prim.bytes;
-        for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_cptr, &d_crow, &d_cval, &d_cval32})
+        for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_rseg, &d_cptr, &d_crow,
+                                &d_cval, &d_cval32, &d_cseg, &d_rseg32, &d_cseg32})
             t += (int64_t)b->bytes;
         for (const auto &s : sp)
-            t += (int64_t)(s.d_occ0.bytes + s.d_desc.bytes + s.d_gptr.bytes + s.d_gent.bytes);
+            t += (int64_t)(s.d_occ0.bytes + s.d_desc.bytes + s.d_adj_off.bytes +
+                           s.d_chunk_det.bytes + s.d_gptr.bytes + s.d_gpos.bytes);
         return t;
     }
 };
@@ -302,25 +310,60 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
         s.desc[e] = pub_desc[s.pub_of[e]];
         s.n_by_degree[s.desc[e].s]++;
     }
-    // aggregation lists: target t = h[a]*M + p[b] <- (d, a, b)
+    // Derivative aggregation: the s*s scaled adjugate entries of determinant d
+    // occupy slots adj_off[d] + a*s + b of a staging buffer; determinants are
+    // cut into chunks whose slots fit kAdjChunk; per chunk, every target
+    // t = h[a]*M + p[b] gets the list of its slots (in determinant order).
+    s.adj_off.assign(s.U + 1, 0);
+    for (int64_t e = 0; e < s.U; ++e) s.adj_off[e + 1] = s.adj_off[e] + s.desc[e].s * s.desc[e].s;
+    s.chunk_det.assign(1, 0);
+    for (int64_t e = 0; e < s.U; ++e)
+        if (s.adj_off[e + 1] - s.adj_off[s.chunk_det.back()] > kAdjChunk)
+            s.chunk_det.push_back((int32_t)e);
+    s.chunk_det.push_back((int32_t)s.U);
+    const int nchunk = (int)s.chunk_det.size() - 1;
     const int64_t nt = (int64_t)n * n_mo;
-    s.gptr.assign(nt + 1, 0);
-    for (int64_t e = 0; e < s.U; ++e) {
-        const DetDesc &D = s.desc[e];
-        for (int a = 0; a < D.s; ++a)
-            for (int b = 0; b < D.s; ++b) s.gptr[(int64_t)D.h[a] * n_mo + D.p[b] + 1]++;
+    s.gptr.assign((size_t)nchunk * (nt + 1), 0);
+    s.gpos.assign(s.adj_off[s.U], 0);
+    int64_t filled = 0;
+    for (int k = 0; k < nchunk; ++k) {
+        int32_t *gp = s.gptr.data() + (size_t)k * (nt + 1);
+        const int32_t base = s.adj_off[s.chunk_det[k]];
+        std::vector<int32_t> cnt(nt + 1, 0);
+        for (int64_t e = s.chunk_det[k]; e < s.chunk_det[k + 1]; ++e) {
+            const DetDesc &D = s.desc[e];
+            for (int a = 0; a < D.s; ++a)
+                for (int b = 0; b < D.s; ++b) cnt[(int64_t)D.h[a] * n_mo + D.p[b] + 1]++;
+        }
+        gp[0] = (int32_t)filled;
+        for (int64_t t = 0; t < nt; ++t) gp[t + 1] = gp[t] + cnt[t + 1];
+        std::vector<int32_t> fill(gp, gp + nt);
+        for (int64_t e = s.chunk_det[k]; e < s.chunk_det[k + 1]; ++e) {
+            const DetDesc &D = s.desc[e];
+            for (int a = 0; a < D.s; ++a)
+                for (int b = 0; b < D.s; ++b) {
+                    const int64_t t = (int64_t)D.h[a] * n_mo + D.p[b];
+                    s.gpos[fill[t]++] = (uint16_t)(s.adj_off[e] - base + a * D.s + b);
+                }
+        }
+        filled = gp[nt];
     }
-    for (int64_t t = 0; t < nt; ++t) s.gptr[t + 1] += s.gptr[t];
-    s.gent.assign(s.gptr[nt], 0);
-    std::vector<int32_t> fill(s.gptr.begin(), s.gptr.end() - 1);
-    for (int64_t e = 0; e < s.U; ++e) {
-        const DetDesc &D = s.desc[e];
-        for (int a = 0; a < D.s; ++a)
-            for (int b = 0; b < D.s; ++b) {
-                const int64_t t = (int64_t)D.h[a] * n_mo + D.p[b];
-                s.gent[fill[t]++] = ((uint32_t)e << 8) | ((uint32_t)a << 4) | (uint32_t)b;
-            }
+}
+
+// Segments of the CSR rows (CSC columns) by chunks of kSpmmCols gathered entries.
+std::vector<int32_t> chunk_segments(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
+                                    int64_t rows, int64_t cols, int32_t width, int32_t &nch) {
+    nch = (int32_t)std::max<int64_t>(1, (cols + width - 1) / width);
+    std::vector<int32_t> seg((size_t)(nch + 1) * rows);
+    for (int64_t i = 0; i < rows; ++i) {
+        int32_t k = ptr[i];
+        for (int c = 0; c < nch; ++c) {
+            seg[(size_t)c * rows + i] = k;
+            while (k < ptr[i + 1] && idx[k] < (c + 1) * width) ++k;
+        }
+        seg[(size_t)nch * rows + i] = ptr[i + 1];
     }
+    return seg;
 }
 
 template <typename Fn>
@@ -353,6 +396,7 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     const int nmax = std::max(c->n_up, c->n_dn);
     const int64_t Upad = (c->sp[0].U + 63) / 64 * 64, Vpad = (c->sp[1].U + 63) / 64 * 64;
     const int64_t RV = Upad + Vpad;
+    const int64_t Wld = (W + 63) / 64 * 64;
     c->w_phi.alloc(sizeof(double) * W * N * 5 * M);
     c->w_E.alloc(sizeof(int32_t) * W * 2 * M);
     c->w_X.alloc(sizeof(double) * W * 2 * nmax * nmax);
@@ -362,14 +406,17 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     c->w_sign0.alloc(sizeof(double) * W * 2);
     c->w_flag.alloc(sizeof(int32_t) * W * 2);
     c->w_K.alloc(sizeof(int32_t) * W * 2);
-    c->w_R64.alloc(sizeof(double) * W * RV);
-    c->w_R32.alloc(sizeof(float) * W * RV);
-    c->w_uv64.alloc(sizeof(double) * W * RV);
-    c->w_uv32.alloc(sizeof(float) * W * RV);
-    c->w_psi64.alloc(sizeof(double) * W);
-    c->w_psi32.alloc(sizeof(float) * W);
+    c->w_R64.alloc(sizeof(double) * Wld * RV);
+    c->w_R32.alloc(sizeof(float) * Wld * RV);
+    c->w_uv64.alloc(sizeof(double) * Wld * RV);
+    c->w_uv32.alloc(sizeof(float) * Wld * RV);
+    c->w_psi64.alloc(sizeof(double) * W * kPsiParts);
+    c->w_Rexp.alloc(sizeof(int32_t) * Wld * RV);
+    c->w_Kmax.alloc(sizeof(int32_t) * W * 2);
+    c->w_dpart.alloc(sizeof(double) * W * kDirectSplit * N * 4);
     Work &k = c->wk;
     k.W = W;
+    k.Wld = Wld;
     k.M = M;
     k.N = N;
     k.nmax = nmax;
@@ -389,7 +436,9 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     k.uv64 = c->w_uv64.as<double>();
     k.uv32 = c->w_uv32.as<float>();
     k.psi64 = c->w_psi64.as<double>();
-    k.psi32 = c->w_psi32.as<float>();
+    k.Rexp = c->w_Rexp.as<int32_t>();
+    k.Kmax = c->w_Kmax.as<int32_t>();
+    k.dpart = c->w_dpart.as<double>();
     c->wcap = W;
 }
 
@@ -473,7 +522,10 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
         require(n_det >= 1 && n_det <= INT32_MAX, MDET_EDIM, "n_det out of range");
         require(n_up >= n_dn, MDET_ESPIN, "n_up < n_dn: the up spin must hold the larger count");
         require(n_dn >= 1 && n_up <= MDET_MAX_SPIN_ELEC, MDET_EDIM, "electron count out of range");
+        require(n_det <= (int64_t)INT32_MAX / 2, MDET_EDIM, "n_det too large");
         require(n_up <= ctx->n_mo, MDET_EDIM, "more electrons of one spin than orbitals");
+        require((int64_t)n_up * ctx->n_mo <= 8192, MDET_EDIM,
+                "n_up * n_mo above 8192 (per-walker tables must fit in LDS)");
         require(n_int == (ctx->n_mo + 63) / 64, MDET_EORBITAL, "n_int must equal ceil(n_mo/64)");
         for (int64_t k = 0; k < n_det; ++k)
             require(std::isfinite(c[k]), MDET_EINVAL, "non-finite coefficient");
@@ -549,11 +601,18 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
         }
         std::vector<float> rval32(rval.begin(), rval.end()), cval32(cval.begin(), cval.end());
 
+        int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
+        std::vector<int32_t> rseg = chunk_segments(rptr, rcol, U, V, kSpmmCols64, nch_r);
+        std::vector<int32_t> cseg = chunk_segments(cptr, crow, V, U, kSpmmCols64, nch_c);
+        std::vector<int32_t> rseg32 = chunk_segments(rptr, rcol, U, V, kSpmmCols32, nch_r32);
+        std::vector<int32_t> cseg32 = chunk_segments(cptr, crow, V, U, kSpmmCols32, nch_c32);
         for (int s = 0; s < 2 && !ctx->host_only; ++s) {
             sp[s].d_occ0.upload(sp[s].occ0);
             sp[s].d_desc.upload(sp[s].desc);
+            sp[s].d_adj_off.upload(sp[s].adj_off);
+            sp[s].d_chunk_det.upload(sp[s].chunk_det);
             sp[s].d_gptr.upload(sp[s].gptr);
-            sp[s].d_gent.upload(sp[s].gent);
+            sp[s].d_gpos.upload(sp[s].gpos);
         }
         if (!ctx->host_only) {
             ctx->d_rptr.upload(rptr);
@@ -564,7 +623,15 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->d_crow.upload(crow);
             ctx->d_cval.upload(cval);
             ctx->d_cval32.upload(cval32);
+            ctx->d_rseg.upload(rseg);
+            ctx->d_cseg.upload(cseg);
+            ctx->d_rseg32.upload(rseg32);
+            ctx->d_cseg32.upload(cseg32);
         }
+        ctx->nch_r = nch_r;
+        ctx->nch_c = nch_c;
+        ctx->nch_r32 = nch_r32;
+        ctx->nch_c32 = nch_c32;
         for (int s = 0; s < 2; ++s) {
             ctx->sp[s].n = sp[s].n;
             ctx->sp[s].U = sp[s].U;
@@ -575,12 +642,16 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->sp[s].pub_of.swap(sp[s].pub_of);
             ctx->sp[s].desc.swap(sp[s].desc);
             for (int k = 0; k <= MDET_MAX_DEGREE; ++k) ctx->sp[s].n_by_degree[k] = sp[s].n_by_degree[k];
+            ctx->sp[s].adj_off.swap(sp[s].adj_off);
+            ctx->sp[s].chunk_det.swap(sp[s].chunk_det);
             ctx->sp[s].gptr.swap(sp[s].gptr);
-            ctx->sp[s].gent.swap(sp[s].gent);
+            ctx->sp[s].gpos.swap(sp[s].gpos);
             std::swap(ctx->sp[s].d_occ0, sp[s].d_occ0);
             std::swap(ctx->sp[s].d_desc, sp[s].d_desc);
+            std::swap(ctx->sp[s].d_adj_off, sp[s].d_adj_off);
+            std::swap(ctx->sp[s].d_chunk_det, sp[s].d_chunk_det);
             std::swap(ctx->sp[s].d_gptr, sp[s].d_gptr);
-            std::swap(ctx->sp[s].d_gent, sp[s].d_gent);
+            std::swap(ctx->sp[s].d_gpos, sp[s].d_gpos);
         }
         ctx->row_i.swap(row_i);
         ctx->col_j.swap(col_j);
@@ -641,10 +712,13 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
             d.n = ctx->sp[s].n;
             d.e0 = s == 0 ? 0 : ctx->n_up;
             d.U = (int32_t)ctx->sp[s].U;
+            d.nchunk = (int32_t)ctx->sp[s].chunk_det.size() - 1;
             d.occ0 = ctx->sp[s].d_occ0.as<int32_t>();
             d.desc = ctx->sp[s].d_desc.as<DetDesc>();
+            d.adj_off = ctx->sp[s].d_adj_off.as<int32_t>();
+            d.chunk_det = ctx->sp[s].d_chunk_det.as<int32_t>();
             d.gptr = ctx->sp[s].d_gptr.as<int32_t>();
-            d.gent = ctx->sp[s].d_gent.as<uint32_t>();
+            d.gpos = ctx->sp[s].d_gpos.as<uint16_t>();
         }
         a.C.U = (int32_t)ctx->sp[0].U;
         a.C.V = (int32_t)ctx->sp[1].U;
@@ -657,6 +731,14 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
         a.C.crow = ctx->d_crow.as<int32_t>();
         a.C.cval = ctx->d_cval.as<double>();
         a.C.cval32 = ctx->d_cval32.as<float>();
+        a.C.rseg64 = ctx->d_rseg.as<int32_t>();
+        a.C.cseg64 = ctx->d_cseg.as<int32_t>();
+        a.C.rseg32 = ctx->d_rseg32.as<int32_t>();
+        a.C.cseg32 = ctx->d_cseg32.as<int32_t>();
+        a.C.nch_r64 = ctx->nch_r;
+        a.C.nch_c64 = ctx->nch_c;
+        a.C.nch_r32 = ctx->nch_r32;
+        a.C.nch_c32 = ctx->nch_c32;
         a.wk = ctx->wk;
         a.W = n_walk;
         a.R = R_dev;

@@ -33,35 +33,54 @@ struct DetDesc {
 };
 static_assert(sizeof(DetDesc) == 16, "DetDesc layout");
 
+// Capacity (doubles) of the LDS staging buffer that holds the scaled
+// adjugates of one chunk of determinants during the derivative aggregation.
+constexpr int kAdjChunk = 4096;
+// Sparse combination: a tile of 64 walkers (one per lane) stages the
+// gathered vector in LDS by chunks of kSpmmCols64 (FP64) or kSpmmCols32
+// (FP32) entries, 128 KB either way.
+constexpr int kSpmmTile = 64;
+constexpr int kSpmmCols64 = 256;
+constexpr int kSpmmCols32 = 512;
+
 // Device view of one spin channel of the expansion.
 struct SpinDev {
     int32_t n;            // electrons of this spin
     int32_t e0;           // first electron index of this spin
     int32_t U;            // distinct determinants
-    int32_t pad;
+    int32_t nchunk;       // adjugate chunks
     const int32_t *occ0;  // [n] reference occupied orbitals, ascending
     const DetDesc *desc;  // [U] in execution order (ascending degree)
-    const int32_t *gptr;  // [n*M+1] aggregation lists, target t = c*M + m
-    const uint32_t *gent; // entries: d_exec << 8 | a << 4 | b
+    const int32_t *adj_off;    // [U+1] first adjugate slot of each determinant (sum of s^2)
+    const int32_t *chunk_det;  // [nchunk+1] determinant range of each chunk
+    const int32_t *gptr;       // [nchunk][n*M+1] per-chunk gather lists, target t = c*M + m
+    const uint16_t *gpos;      // adjugate slot (chunk-local) of each list entry
 };
 
-// Device view of the sparse coefficient matrix in execution indices.
+// Device view of the sparse coefficient matrix in execution indices.  The
+// CSR rows (and CSC columns) are cut into segments by chunks of gathered
+// entries: seg[c*U + i] is the first entry of row i whose column lies in
+// chunk c (seg[nch*U + i] = end of row i).  One set per chunk width.
 struct SparseDev {
     int32_t U, V;
     int64_t Z;
+    int32_t nch_r64, nch_c64, nch_r32, nch_c32;
     const int32_t *rptr;   // [U+1] CSR (rows = up determinants)
     const int32_t *rcol;   // [Z]
     const double *rval;    // [Z]
     const float *rval32;   // [Z]
+    const int32_t *rseg64, *rseg32;  // [(nch+1)*U]
     const int32_t *cptr;   // [V+1] CSC (columns = down determinants)
     const int32_t *crow;   // [Z]
     const double *cval;    // [Z]
     const float *cval32;   // [Z]
+    const int32_t *cseg64, *cseg32;  // [(nch+1)*V]
 };
 
 // Per-call work buffers (device), sized for W walkers.
 struct Work {
     int64_t W;
+    int64_t Wld;       // leading dimension (walkers) of the walker-minor vectors
     int32_t M, N, nmax, Upad, Vpad;
     double *phi;       // [W][N][5][M] orbitals and derivatives, column-scaled
     int32_t *E;        // [W][2][M] per-spin column exponents
@@ -72,13 +91,21 @@ struct Work {
     double *sign0;     // [W][2]
     int32_t *flag;     // [W][2] 0 table method, 1 ill-conditioned, 2 singular
     int32_t *K;        // [W][2] exponent shift of the ratio vectors
-    double *R64;       // [W][Upad+Vpad]
-    float *R32;        // [W][Upad+Vpad]
-    double *uv64;      // [W][Upad+Vpad]  u (up part) then v (down part)
-    float *uv32;       // [W][Upad+Vpad]
-    double *psi64;     // [W]
-    float *psi32;      // [W]
+    double *R64;       // [Upad+Vpad][Wld] walker-minor: R_up rows then R_dn rows
+    float *R32;        // [Upad+Vpad][Wld]
+    double *uv64;      // [Upad+Vpad][Wld] u (up rows) then v (down rows)
+    float *uv32;       // [Upad+Vpad][Wld]
+    double *psi64;     // [W][kPsiParts] partial sums of psi (FP64 in both precisions)
+    int32_t *Rexp;     // [Upad+Vpad][Wld] direct-LU fallback: exponents of the determinants
+    int32_t *Kmax;     // [W][2] direct-LU fallback: largest exponent (integer max)
+    double *dpart;     // [W][kDirectSplit][N][4] direct-LU fallback: derivative partial sums
 };
+
+// Blocks per (walker, spin) of the direct-LU fallback.
+constexpr int kDirectSplit = 4;
+
+// Row splits of the sparse combination per walker tile (partial psi sums).
+constexpr int kPsiParts = 16;
 
 struct KernelArgs {
     int32_t n_up, n_dn, N, M, P, nmax;
@@ -91,6 +118,7 @@ struct KernelArgs {
     const double *R;          // [W][N][3]
     const int8_t *max_degree; // [W] or null
     int32_t precision;
+    int32_t psi_nparts;       // row splits used by the sparse combination
     double *sign_out, *logabs_out, *gl_out;
     int32_t *wstatus;
 };

@@ -23,6 +23,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <climits>
+
 namespace mdet {
 
 namespace {
@@ -154,25 +157,191 @@ __device__ double cofactor(const double *m, int s, int a, int b) {
     return ((a + b) & 1) ? -d : d;
 }
 
-__device__ __forceinline__ void load_excitation(const DetDesc &D, const double *T, int M,
-                                                double *mat) {
-    const int s = D.s;
-    for (int a = 0; a < s; ++a)
-        for (int b = 0; b < s; ++b) mat[a * s + b] = T[D.h[a] * M + D.p[b]];
-}
-
 __device__ __forceinline__ int delta_exponent(const DetDesc &D, const int *Ex, const int *occ0) {
     int dx = 0;
     for (int a = 0; a < D.s; ++a) dx += Ex[D.p[a]] - Ex[occ0[D.h[a]]];
     return dx;
 }
 
-__device__ __forceinline__ size_t rv_offset(const KernelArgs &a, int sp) {
-    return sp == 0 ? 0 : (size_t)a.wk.Upad;
+// Gauss-Jordan inversion with partial pivoting of an S x S matrix (row-major),
+// fully unrolled so the matrix lives in registers.  Returns false on an exactly
+// zero pivot.  det receives the determinant (product of pivots and row-swap signs).
+template <int S>
+__device__ __forceinline__ bool gj_inverse(const double *m, double *inv, double &det) {
+    double a[S][S], b[S][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            a[i][k] = m[i * S + k];
+            b[i][k] = (i == k) ? 1.0 : 0.0;
+        }
+    det = 1.0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        int p = j;
+        double best = fabs(a[j][j]);
+#pragma unroll
+        for (int i = j + 1; i < S; ++i)
+            if (fabs(a[i][j]) > best) {
+                best = fabs(a[i][j]);
+                p = i;
+            }
+        if (!(best > 0.0)) return false;
+#pragma unroll
+        for (int i = j + 1; i < S; ++i)
+            if (i == p) {
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    double t = a[i][k];
+                    a[i][k] = a[j][k];
+                    a[j][k] = t;
+                    t = b[i][k];
+                    b[i][k] = b[j][k];
+                    b[j][k] = t;
+                }
+                det = -det;
+            }
+        const double piv = a[j][j];
+        det *= piv;
+        const double r = 1.0 / piv;
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+            a[j][k] *= r;
+            b[j][k] *= r;
+        }
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (i == j) continue;
+            const double f = a[i][j];
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                a[i][k] -= f * a[j][k];
+                b[i][k] -= f * b[j][k];
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int k = 0; k < S; ++k) inv[i * S + k] = b[i][k];
+    return true;
 }
 
-__device__ __forceinline__ size_t rv_stride(const KernelArgs &a) {
-    return (size_t)a.wk.Upad + a.wk.Vpad;
+// LU (partial pivoting) determinant of an S x S matrix, unrolled.
+template <int S>
+__device__ __forceinline__ double det_lu(const double *m) {
+    double a[S][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int k = 0; k < S; ++k) a[i][k] = m[i * S + k];
+    double det = 1.0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        int p = j;
+        double best = fabs(a[j][j]);
+#pragma unroll
+        for (int i = j + 1; i < S; ++i)
+            if (fabs(a[i][j]) > best) {
+                best = fabs(a[i][j]);
+                p = i;
+            }
+        if (!(best > 0.0)) return 0.0;
+#pragma unroll
+        for (int i = j + 1; i < S; ++i)
+            if (i == p) {
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    const double t = a[i][k];
+                    a[i][k] = a[j][k];
+                    a[j][k] = t;
+                }
+                det = -det;
+            }
+        det *= a[j][j];
+#pragma unroll
+        for (int i = j + 1; i < S; ++i) {
+            const double l = a[i][j] / a[j][j];
+#pragma unroll
+            for (int k = j + 1; k < S; ++k) a[i][k] -= l * a[j][k];
+        }
+    }
+    return det;
+}
+
+// Offsets of the walker-minor vectors R, u, v: entry d of spin sp for walker w
+// sits at ((sp ? Upad : 0) + d) * Wld + w.
+__device__ __forceinline__ size_t rv_index(const KernelArgs &a, int sp, int d, int w) {
+    return ((size_t)(sp ? a.wk.Upad : 0) + d) * (size_t)a.wk.Wld + w;
+}
+
+// psi of walker w: the row-split partial sums of the sparse combination
+// (accumulated in FP64 in both precisions), added in a fixed order
+__device__ __forceinline__ double psi_value(const KernelArgs &a, int w) {
+    double s = 0.0;
+    for (int k = 0; k < a.psi_nparts; ++k) s += a.wk.psi64[(size_t)w * kPsiParts + k];
+    return s;
+}
+
+// s x s excitation matrix M[a][b] = T[h_a][p_b], compile-time s
+template <int S>
+__device__ __forceinline__ void load_exc(const DetDesc &D, const double *T, int M, double *m) {
+#pragma unroll
+    for (int a2 = 0; a2 < S; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < S; ++b2) m[a2 * S + b2] = T[D.h[a2] * M + D.p[b2]];
+}
+
+// eps_d det M_d (the ratio D_d / D_0 before the exponent shift)
+template <int S>
+__device__ __forceinline__ double exc_ratio(const DetDesc &D, const double *T, int M) {
+    double m[S * S];
+    load_exc<S>(D, T, M, m);
+    double d;
+    if constexpr (S == 1) d = m[0];
+    else if constexpr (S == 2) d = det2(m[0], m[1], m[2], m[3]);
+    else d = det_lu<S>(m);
+    return (double)D.eps * d;
+}
+
+__device__ __forceinline__ double ratio_any(const DetDesc &D, const double *T, int M) {
+    switch (D.s) {
+    case 0: return (double)D.eps;
+    case 1: return exc_ratio<1>(D, T, M);
+    case 2: return exc_ratio<2>(D, T, M);
+    case 3: return exc_ratio<3>(D, T, M);
+    default: return exc_ratio<4>(D, T, M);
+    }
+}
+
+// coef * C_ab of M_d into dst[a*S + b] (C_ab = adj[b][a]), compile-time s
+template <int S>
+__device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int M, double coef,
+                                          double *dst) {
+    double m[S * S], adj[S * S];
+    load_exc<S>(D, T, M, m);
+    if constexpr (S == 1) {
+        adj[0] = 1.0;
+    } else if constexpr (S == 2) {
+        adj[0] = m[3];
+        adj[1] = -m[1];
+        adj[2] = -m[2];
+        adj[3] = m[0];
+    } else {
+        double det = 0.0;
+        if (gj_inverse<S>(m, adj, det)) {
+#pragma unroll
+            for (int t = 0; t < S * S; ++t) adj[t] *= det;
+        } else {
+            for (int a2 = 0; a2 < S; ++a2)  // exactly singular: explicit cofactors
+                for (int b2 = 0; b2 < S; ++b2) adj[b2 * S + a2] = cofactor(m, S, a2, b2);
+        }
+    }
+#pragma unroll
+    for (int a2 = 0; a2 < S; ++a2)
+#pragma unroll
+        for (int b2 = 0; b2 < S; ++b2) dst[a2 * S + b2] = coef * adj[b2 * S + a2];
 }
 
 }  // namespace
@@ -267,6 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         __syncthreads();
     }
     const size_t ws = (size_t)w * 2 + sp;
+    if (tid == 0) a.wk.Kmax[ws] = INT_MIN;
     if (s_state) {
         if (tid == 0) {
             a.wk.flag[ws] = 2;
@@ -367,6 +537,7 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
 
 // ---------------------------------------------------------------------------
 // K4: ratios R_d / 2^K of every distinct determinant (table method).
+// One block per (walker, spin); one thread per determinant.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
@@ -385,205 +556,147 @@ __global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
     for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
     __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
-    double *R64 = a.wk.R64 + (size_t)w * rv_stride(a) + rv_offset(a, sp);
     int kmax = INT_MIN;
     for (int d = tid; d < S.U; d += kBlock) {
         const DetDesc D = S.desc[d];
         double r = 0.0;
         if (D.s <= dmax) {
-            double mat[16];
-            load_excitation(D, T, M, mat);
-            r = (double)D.eps * small_det(mat, D.s);
+            r = ratio_any(D, T, M);
             if (r != 0.0) kmax = max(kmax, expo(r) + delta_exponent(D, Ex, occ0));
         }
-        R64[d] = r;
+        a.wk.R64[rv_index(a, sp, d, w)] = r;
     }
     int K = block_max_int(kmax, red);
     if (K == INT_MIN) K = 0;
     if (tid == 0) a.wk.K[ws] = K;
-    float *R32 = a.wk.R32 + (size_t)w * rv_stride(a) + rv_offset(a, sp);
     for (int d = tid; d < S.U; d += kBlock) {
         const DetDesc D = S.desc[d];
-        const double r = ldexp(R64[d], delta_exponent(D, Ex, occ0) - K);
-        if (a.precision == MDET_MIXED) R32[d] = (float)r;
-        else R64[d] = r;
+        const size_t o = rv_index(a, sp, d, w);
+        const double r = ldexp(a.wk.R64[o], delta_exponent(D, Ex, occ0) - K);
+        if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
+        else a.wk.R64[o] = r;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Direct-LU fallback: one wave per determinant, LU of the scaled S_d.
+// K5: the two sparse products of Sec. 2.4 for a tile of 64 walkers (one per
+// lane), 16 waves per block:
+//   pass 0:  u = C R_dn  (CSR rows, gathering R_dn)  and the psi partials R_up . u
+//   pass 1:  v = C^T R_up (CSC columns, gathering R_up)
+// A wave owns whole rows, so the entries of C are wave-uniform (scalar loads)
+// and each one feeds 64 fused multiply-adds; the gathered vector of the 64
+// walkers sits in LDS, CC entries at a time.  The kernel is bound by LDS
+// bandwidth, which leaves ALU slack: the FP32 variant spends it on a
+// compensated (TwoSum) accumulation.  grid.x = walker tiles x row splits,
+// grid.y = pass.
 // ---------------------------------------------------------------------------
-namespace {
+constexpr int kSpmmWaves = 16;
 
-// Builds S_d (slot order) into Sm[n][n] for determinant D, lanes over rows.
-// Returns the wave-uniform (mantissa, exponent) of det S_d' (slot order,
-// scaled columns) times eps; mant == 0 for an exactly singular matrix.  Also
-// leaves the LU factors and pivots in Sm / piv for a later inverse.
-__device__ void wave_lu_det(const DetDesc &D, const int *occ0, const double *phig, int e0,
-                            int M, int n, int lane, double *Sm, int *piv, int *occ,
-                            double &mant, int &ex) {
-    if (lane < n) {
-        int o = occ0[lane];
-        for (int a = 0; a < D.s; ++a)
-            if (D.h[a] == lane) o = D.p[a];
-        occ[lane] = o;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (lane < n)
-        for (int c = 0; c < n; ++c) Sm[lane * n + c] = phig[(size_t)(e0 + lane) * 5 * M + occ[c]];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    double m = (double)D.eps;
-    int k = 0;
-    bool sing = false;
-    for (int j = 0; j < n; ++j) {
-        double v = (lane >= j && lane < n) ? fabs(Sm[lane * n + j]) : -1.0;
-        int id = lane;
-        for (int off = 32; off > 0; off >>= 1) {
-            const double v2 = __shfl_xor(v, off, 64);
-            const int i2 = __shfl_xor(id, off, 64);
-            if (v2 > v || (v2 == v && i2 < id)) {
-                v = v2;
-                id = i2;
-            }
-        }
-        if (!(v > 0.0)) {
-            sing = true;
-            break;
-        }
-        if (lane == 0) piv[j] = id;
-        if (id != j && lane < n) {
-            const double t = Sm[j * n + lane];
-            Sm[j * n + lane] = Sm[id * n + lane];
-            Sm[id * n + lane] = t;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double dj = Sm[j * n + j];
-        if (id != j) m = -m;
-        m *= dj;
-        int kk;
-        m = frexp(m, &kk);
-        k += kk;
-        if (lane > j && lane < n) {
-            const double l = Sm[lane * n + j] / dj;
-            Sm[lane * n + j] = l;
-            for (int c = j + 1; c < n; ++c) Sm[lane * n + c] -= l * Sm[j * n + c];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (sing) {
-        mant = 0.0;
-        ex = 0;
-    } else {
-        mant = m;
-        ex = k;
-    }
-}
-
-}  // namespace
-
-__global__ void __launch_bounds__(kBlock) k_direct_ratios(KernelArgs a) {
-    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
-    const size_t ws = (size_t)w * 2 + sp;
-    if (a.wk.flag[ws] == 0) return;
-    const SpinDev S = a.sp[sp];
-    const int n = S.n, M = a.M, tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    constexpr int kWaves = kBlock / 64;
-    __shared__ double Sm[kWaves][kMaxN * kMaxN];
-    __shared__ int piv[kWaves][kMaxN];
-    __shared__ int occ[kWaves][kMaxN];
-    __shared__ int occ0[kMaxN];
-    __shared__ int red[kBlock];
-    extern __shared__ double lds[];
-    int *Ex = (int *)lds;
-    for (int m = tid; m < M; m += kBlock) Ex[m] = a.wk.E[ws * M + m];
-    for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
-    __syncthreads();
-    const double *phig = a.wk.phi + (size_t)w * a.N * 5 * M;
-    const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
-    int kmax = INT_MIN;
-    // pass 1: largest exponent
-    for (int d = wave; d < S.U; d += kWaves) {
-        const DetDesc D = S.desc[d];
-        if (D.s > dmax) continue;
-        double mant;
-        int ex;
-        wave_lu_det(D, occ0, phig, S.e0, M, n, lane, Sm[wave], piv[wave], occ[wave], mant, ex);
-        if (mant != 0.0) {
-            int sx = 0;
-            for (int c = 0; c < n; ++c) sx += Ex[occ[wave][c]];
-            kmax = max(kmax, ex + sx);
-        }
-    }
-    int K = block_max_int(kmax, red);
-    if (K == INT_MIN) K = 0;
-    if (tid == 0) {
-        a.wk.K[ws] = K;
-        a.wk.logdet0[ws] = 0.0;
-        a.wk.sign0[ws] = 1.0;
-    }
-    double *R64 = a.wk.R64 + (size_t)w * rv_stride(a) + rv_offset(a, sp);
-    float *R32 = a.wk.R32 + (size_t)w * rv_stride(a) + rv_offset(a, sp);
-    for (int d = wave; d < S.U; d += kWaves) {
-        const DetDesc D = S.desc[d];
-        double r = 0.0;
-        if (D.s <= dmax) {
-            double mant;
-            int ex;
-            wave_lu_det(D, occ0, phig, S.e0, M, n, lane, Sm[wave], piv[wave], occ[wave], mant, ex);
-            int sx = 0;
-            for (int c = 0; c < n; ++c) sx += Ex[occ[wave][c]];
-            r = ldexp(mant, ex + sx - K);
-        }
-        if (lane == 0) {
-            if (a.precision == MDET_MIXED) R32[d] = (float)r;
-            else R64[d] = r;
-        }
-    }
-    for (int idx = tid; idx < 4 * n; idx += kBlock)
-        a.wk.g0[((size_t)w * a.N + S.e0 + (idx >> 2)) * 4 + (idx & 3)] = 0.0;
-}
-
-// ---------------------------------------------------------------------------
-// K5: u = C R_dn, v = C^T R_up, psi = R_up . u   (one block per walker)
-// ---------------------------------------------------------------------------
+// s + x with the rounding error of the addition carried in comp (TwoSum)
 template <typename F>
-__global__ void __launch_bounds__(kBlock) k_spmm(KernelArgs a, const F *R, F *uv, F *psi,
-                                                  const F *rval, const F *cval) {
-    const int w = blockIdx.x, tid = threadIdx.x;
-    __shared__ F red[kBlock];
-    const SparseDev C = a.C;
-    const size_t st = rv_stride(a);
-    const F *Rup = R + (size_t)w * st;
-    const F *Rdn = Rup + a.wk.Upad;
-    F *u = uv + (size_t)w * st;
-    F *v = u + a.wk.Upad;
-    F part = 0;
-    for (int i = tid; i < C.U; i += kBlock) {
-        F acc = 0;
-        for (int k = C.rptr[i]; k < C.rptr[i + 1]; ++k) acc += rval[k] * Rdn[C.rcol[k]];
-        u[i] = acc;
-        part += Rup[i] * acc;
+__device__ __forceinline__ void two_sum_acc(F &s, F &comp, F x) {
+#pragma clang fp contract(off)
+    const F t = s + x;
+    const F z = t - s;
+    comp += (s - (t - z)) + (x - z);
+    s = t;
+}
+
+template <typename F, int CC, bool COMP>
+__global__ void __launch_bounds__(64 * kSpmmWaves)
+    k_spmm(KernelArgs a, const F *__restrict__ R, F *__restrict__ uv,
+           const F *__restrict__ rval, const F *__restrict__ cval,
+           const int32_t *__restrict__ rcol, const int32_t *__restrict__ crow,
+           const int32_t *__restrict__ rseg, const int32_t *__restrict__ cseg, int nch_r, int nch_c,
+           int rsplit) {
+    __shared__ F G[CC * kSpmmTile];
+    __shared__ double red[kSpmmWaves][kSpmmTile];
+    const int pass = blockIdx.y;
+    const int tile = blockIdx.x / rsplit, rs = blockIdx.x - tile * rsplit;
+    const int W = (int)a.W;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int w0 = tile * kSpmmTile, w = w0 + lane;
+    const bool active = w < W;
+    const int nrows = pass ? a.C.V : a.C.U;
+    const int ncols = pass ? a.C.U : a.C.V;
+    const int nch = pass ? nch_c : nch_r;
+    const int32_t *__restrict__ idx = pass ? crow : rcol;
+    const int32_t *__restrict__ seg = pass ? cseg : rseg;
+    const F *__restrict__ val = pass ? cval : rval;
+    const size_t Wld = (size_t)a.wk.Wld;
+    const size_t goff = pass ? 0 : (size_t)a.wk.Upad;   // gathered: R_up (pass 1) / R_dn (pass 0)
+    const size_t ooff = pass ? (size_t)a.wk.Upad : 0;   // written: v / u
+    const int r0 = (int)((int64_t)nrows * rs / rsplit), r1 = (int)((int64_t)nrows * (rs + 1) / rsplit);
+    double part = 0.0;
+    for (int c = 0; c < nch; ++c) {
+        const int cb = c * CC;
+        const int nc = min(CC, ncols - cb);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nc * kSpmmTile; t += 64 * kSpmmWaves) {
+            const int jj = t >> 6, ww = t & 63;
+            G[t] = (w0 + ww < W) ? R[(goff + cb + jj) * Wld + w0 + ww] : (F)0;
+        }
+        __syncthreads();
+        for (int i = r0 + wave; i < r1; i += kSpmmWaves) {
+            const int kb = seg[(size_t)c * nrows + i], ke = seg[(size_t)(c + 1) * nrows + i];
+            const size_t o = (ooff + i) * Wld + w;
+            F s = (c == 0 || !active) ? (F)0 : uv[o];
+            // 8 nonzeros per step: their scalar loads and LDS reads are all in
+            // flight before the first multiply-add; two independent sums
+            F s2 = 0, comp = 0, comp2 = 0;
+            int k = kb;
+            for (; k + 8 <= ke; k += 8) {
+                int jx[8];
+                F vx[8], gx[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    jx[t] = idx[k + t];
+                    vx[t] = val[k + t];
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) gx[t] = G[((jx[t] - cb) << 6) + lane];
+#pragma unroll
+                for (int t = 0; t < 8; t += 2) {
+                    if constexpr (COMP) {
+                        two_sum_acc(s, comp, vx[t] * gx[t]);
+                        two_sum_acc(s2, comp2, vx[t + 1] * gx[t + 1]);
+                    } else {
+                        s += vx[t] * gx[t];
+                        s2 += vx[t + 1] * gx[t + 1];
+                    }
+                }
+            }
+            for (; k < ke; ++k) {
+                const F x = val[k] * G[((idx[k] - cb) << 6) + lane];
+                if constexpr (COMP) two_sum_acc(s, comp, x);
+                else s += x;
+            }
+            if constexpr (COMP) {
+                two_sum_acc(s, comp, s2);
+                s += comp + comp2;
+            } else {
+                s += s2;
+            }
+            if (active) uv[o] = s;
+            if (pass == 0 && c == nch - 1 && active) part += (double)R[(size_t)i * Wld + w] * (double)s;
+        }
     }
-    for (int j = tid; j < C.V; j += kBlock) {
-        F acc = 0;
-        for (int k = C.cptr[j]; k < C.cptr[j + 1]; ++k) acc += cval[k] * Rup[C.crow[k]];
-        v[j] = acc;
+    if (pass == 0) {
+        red[wave][lane] = part;
+        __syncthreads();
+        if (wave == 0 && active) {
+            double t = 0.0;
+            for (int g = 0; g < kSpmmWaves; ++g) t += red[g][lane];
+            a.wk.psi64[(size_t)w * kPsiParts + rs] = t;
+        }
     }
-    const F s = block_sum<F>(part, red);
-    if (tid == 0) psi[w] = s;
 }
 
 // ---------------------------------------------------------------------------
-// K6: derivative aggregation (table method)
+// K6: derivative aggregation (table method).  Per chunk of determinants the
+// scaled adjugates w_d f_d adj(M_d) are staged in LDS, then every target
+// (slot c, orbital m) sums its slots in a fixed order into Gamma[c][m].
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
@@ -591,46 +704,63 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     if (a.wk.flag[ws] != 0) return;
     const SpinDev S = a.sp[sp];
     const int n = S.n, M = a.M, N = a.N, tid = threadIdx.x;
+    const int nt = n * M;
     extern __shared__ double lds[];
-    double *T = lds;               // [n][M]
-    double *X = T + n * M;         // [n][n]
-    double *Gam = X + n * n;       // [M][n]
-    double *Y = Gam + M * n;       // [M][n]
-    double *Zc = Y + M * n;        // [n][n]
-    int *Ex = (int *)(Zc + n * n); // [M]
-    int *occ0 = Ex + M;            // [n]
+    double *T = lds;                  // [n][M]
+    double *X = T + nt;               // [n][n]
+    double *Gam = X + n * n;          // [n][M]  Gamma[c][m]
+    double *Y = Gam + nt;             // [M][n]
+    double *Zc = Y + nt;              // [n][n]
+    double *cb = Zc + n * n;          // [kAdjChunk]
+    int *Ex = (int *)(cb + kAdjChunk); // [M]
+    int *occ0 = Ex + M;               // [n]
     const double *Tg = a.wk.T + ws * a.nmax * M;
-    for (int idx = tid; idx < n * M; idx += kBlock) T[idx] = Tg[idx];
+    for (int i = tid; i < nt; i += kBlock) {
+        T[i] = Tg[i];
+        Gam[i] = 0.0;
+    }
     const double *Xg = a.wk.X + ws * a.nmax * a.nmax;
-    for (int idx = tid; idx < n * n; idx += kBlock) X[idx] = Xg[idx];
+    for (int i = tid; i < n * n; i += kBlock) X[i] = Xg[i];
     for (int m = tid; m < M; m += kBlock) Ex[m] = a.wk.E[ws * M + m];
     for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
     __syncthreads();
     const int K = a.wk.K[ws];
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
-    const size_t off = (size_t)w * rv_stride(a) + rv_offset(a, sp);
     const bool mixed = a.precision == MDET_MIXED;
-    for (int t = tid; t < n * M; t += kBlock) {
-        const int c = t / M, m = t - c * M;
-        double g = 0.0;
-        for (int q = S.gptr[t]; q < S.gptr[t + 1]; ++q) {
-            const uint32_t ent = S.gent[q];
-            const int d = (int)(ent >> 8), ia = (ent >> 4) & 15, ib = ent & 15;
+    for (int k = 0; k < S.nchunk; ++k) {
+        const int d0 = S.chunk_det[k], d1 = S.chunk_det[k + 1];
+        const int base = S.adj_off[d0];
+        for (int d = d0 + tid; d < d1; d += kBlock) {
             const DetDesc D = S.desc[d];
-            if (D.s > dmax) continue;
-            double mat[16];
-            load_excitation(D, T, M, mat);
-            const double wt = mixed ? (double)a.wk.uv32[off + d] : a.wk.uv64[off + d];
-            const double f = (double)D.eps * pow2(delta_exponent(D, Ex, occ0) - K);
-            g += wt * f * cofactor(mat, D.s, ia, ib);
+            const int s = D.s;
+            if (s == 0) continue;
+            double *dst = cb + (S.adj_off[d] - base);
+            double coef = 0.0;
+            if (s <= dmax) {
+                const size_t o = rv_index(a, sp, d, w);
+                const double wt = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
+                coef = wt * (double)D.eps * pow2(delta_exponent(D, Ex, occ0) - K);
+            }
+            switch (s) {
+            case 1: stage_adj<1>(D, T, M, coef, dst); break;
+            case 2: stage_adj<2>(D, T, M, coef, dst); break;
+            case 3: stage_adj<3>(D, T, M, coef, dst); break;
+            default: stage_adj<4>(D, T, M, coef, dst); break;
+            }
         }
-        Gam[m * n + c] = g;
+        __syncthreads();
+        const int32_t *gp = S.gptr + (size_t)k * (nt + 1);
+        for (int t = tid; t < nt; t += kBlock) {
+            double g = 0.0;
+            for (int q = gp[t]; q < gp[t + 1]; ++q) g += cb[S.gpos[q]];
+            Gam[t] += g;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     for (int idx = tid; idx < M * n; idx += kBlock) {
         const int m = idx / n, e = idx - m * n;
         double s = 0.0;
-        for (int c = 0; c < n; ++c) s += Gam[m * n + c] * X[c * n + e];
+        for (int c = 0; c < n; ++c) s += Gam[c * M + m] * X[c * n + e];
         Y[idx] = s;
     }
     __syncthreads();
@@ -641,117 +771,288 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
         Zc[idx] = s;
     }
     __syncthreads();
-    const double psi = mixed ? (double)a.wk.psi32[w] : a.wk.psi64[w];
+    const double psi = psi_value(a, w);
     const double *phig = a.wk.phi + (size_t)w * N * 5 * M;
     for (int idx = tid; idx < 4 * n; idx += kBlock) {
         const int e = idx >> 2, q = idx & 3;
-        const double *G = phig + (size_t)(S.e0 + e) * 5 * M + (size_t)(1 + q) * M;
+        const double *Gq = phig + (size_t)(S.e0 + e) * 5 * M + (size_t)(1 + q) * M;
         double s1 = 0.0, s2 = 0.0;
-        for (int m = 0; m < M; ++m) s1 += G[m] * Y[m * n + e];
-        for (int c = 0; c < n; ++c) s2 += G[occ0[c]] * Zc[c * n + e];
+        for (int m = 0; m < M; ++m) s1 += Gq[m] * Y[m * n + e];
+        for (int c = 0; c < n; ++c) s2 += Gq[occ0[c]] * Zc[c * n + e];
         const size_t o = ((size_t)w * N + S.e0 + e) * 4 + q;
         a.gl_out[o] = a.wk.g0[o] + (s1 - s2) / psi;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Direct-LU fallback for the derivatives: sum_d w_d R_d grad~D_d/D_d / psi.
+// Direct-LU fallback for an ill-conditioned reference: every determinant of
+// the (walker, spin) by its own LU, one thread per determinant with the
+// NT x NT matrix in registers (NT = electrons of the spin), kDirectSplit
+// blocks per (walker, spin).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_direct_deriv(KernelArgs a) {
-    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
+namespace {
+
+constexpr int kDirectBlock = 128;
+
+// LU with partial pivoting of a[NT][NT] in place; perm[i] = original row of
+// row i.  The determinant is returned as mant * 2^ex (mant = 0 if singular).
+template <int NT>
+__device__ __forceinline__ void lu_regs(double (&a)[NT][NT], int (&perm)[NT], double &mant,
+                                        int &ex) {
+#pragma unroll
+    for (int i = 0; i < NT; ++i) perm[i] = i;
+    double m = 1.0;
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        int p = j;
+        double best = fabs(a[j][j]);
+#pragma unroll
+        for (int i = j + 1; i < NT; ++i)
+            if (fabs(a[i][j]) > best) {
+                best = fabs(a[i][j]);
+                p = i;
+            }
+        if (!(best > 0.0)) {
+            mant = 0.0;
+            ex = 0;
+            return;
+        }
+#pragma unroll
+        for (int i = j + 1; i < NT; ++i)
+            if (i == p) {
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const double t = a[i][c];
+                    a[i][c] = a[j][c];
+                    a[j][c] = t;
+                }
+                const int t = perm[i];
+                perm[i] = perm[j];
+                perm[j] = t;
+                m = -m;
+            }
+        m *= a[j][j];
+        int kk;
+        m = frexp(m, &kk);
+        k += kk;
+#pragma unroll
+        for (int i = j + 1; i < NT; ++i) {
+            const double l = a[i][j] / a[j][j];
+            a[i][j] = l;
+#pragma unroll
+            for (int c = j + 1; c < NT; ++c) a[i][c] -= l * a[j][c];
+        }
+    }
+    mant = m;
+    ex = k;
+}
+
+// occupied orbital of slot c for determinant D (reference with holes replaced)
+__device__ __forceinline__ int slot_orbital(const DetDesc &D, const int *occ0, int c) {
+    int o = occ0[c];
+    for (int t = 0; t < D.s; ++t)
+        if (D.h[t] == c) o = D.p[t];
+    return o;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace
+
+// pass 1: mantissa and exponent of every determinant of the block's range,
+// and the integer maximum of the exponents per (walker, spin)
+template <int NT>
+__global__ void __launch_bounds__(kDirectBlock) k_direct_ratios_t(KernelArgs a, int sp) {
+    const int w = blockIdx.x, part = blockIdx.y;
     const size_t ws = (size_t)w * 2 + sp;
     if (a.wk.flag[ws] == 0) return;
     const SpinDev S = a.sp[sp];
-    const int n = S.n, M = a.M, N = a.N, tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    constexpr int kWaves = kBlock / 64;
-    __shared__ double Sm[kWaves][kMaxN * kMaxN];
-    __shared__ double Xw[kWaves][kMaxN * kMaxN];
-    __shared__ int piv[kWaves][kMaxN];
-    __shared__ int occ[kWaves][kMaxN];
-    __shared__ int occ0[kMaxN];
-    __shared__ double part[kWaves][kMaxN * 4];
+    const int M = a.M, tid = threadIdx.x;
     extern __shared__ double lds[];
-    int *Ex = (int *)lds;
-    for (int m = tid; m < M; m += kBlock) Ex[m] = a.wk.E[ws * M + m];
-    for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
+    double *P0 = lds;                 // [NT][M] scaled orbital values of this spin
+    int *Ex = (int *)(P0 + NT * M);   // [M]
+    int *occ0 = Ex + M;               // [NT]
+    __shared__ int red[kDirectBlock];
+    const double *phig = a.wk.phi + (size_t)w * a.N * 5 * M;
+    for (int i = tid; i < NT * M; i += kDirectBlock) {
+        const int e = i / M, m = i - e * M;
+        P0[i] = phig[(size_t)(S.e0 + e) * 5 * M + m];
+    }
+    for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[ws * M + m];
+    for (int c = tid; c < NT; c += kDirectBlock) occ0[c] = S.occ0[c];
     __syncthreads();
+    const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
+    const int d0 = (int)((int64_t)S.U * part / kDirectSplit);
+    const int d1 = (int)((int64_t)S.U * (part + 1) / kDirectSplit);
+    int kmax = INT_MIN;
+    for (int d = d0 + tid; d < d1; d += kDirectBlock) {
+        const DetDesc D = S.desc[d];
+        double r = 0.0;
+        int rexp = INT_MIN;
+        if (D.s <= dmax) {
+            double A[NT][NT];
+            int perm[NT];
+            int sx = 0;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const int o = slot_orbital(D, occ0, c);
+                sx += Ex[o];
+#pragma unroll
+                for (int e = 0; e < NT; ++e) A[e][c] = P0[e * M + o];
+            }
+            double mant;
+            int ex;
+            lu_regs<NT>(A, perm, mant, ex);
+            if (mant != 0.0) {
+                r = (double)D.eps * mant;
+                rexp = ex + sx;
+                kmax = max(kmax, rexp);
+            }
+        }
+        const size_t o = rv_index(a, sp, d, w);
+        a.wk.R64[o] = r;
+        a.wk.Rexp[o] = rexp;
+    }
+    red[tid] = kmax;
+    __syncthreads();
+    if (tid == 0) {
+        int m = INT_MIN;
+        for (int t = 0; t < kDirectBlock; ++t) m = max(m, red[t]);
+        if (m != INT_MIN) atomicMax(&a.wk.Kmax[ws], m);
+    }
+}
+
+// pass 2: shift every ratio by the (walker, spin) maximum exponent
+__global__ void __launch_bounds__(kBlock) k_direct_scale(KernelArgs a) {
+    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, part = blockIdx.y;
+    const size_t ws = (size_t)w * 2 + sp;
+    if (a.wk.flag[ws] == 0) return;
+    const SpinDev S = a.sp[sp];
+    int K = a.wk.Kmax[ws];
+    if (K == INT_MIN) K = 0;
+    if (part == 0 && threadIdx.x == 0) {
+        a.wk.K[ws] = K;
+        a.wk.logdet0[ws] = 0.0;
+        a.wk.sign0[ws] = 1.0;
+    }
+    const int d0 = (int)((int64_t)S.U * part / kDirectSplit);
+    const int d1 = (int)((int64_t)S.U * (part + 1) / kDirectSplit);
+    for (int d = d0 + threadIdx.x; d < d1; d += kBlock) {
+        const size_t o = rv_index(a, sp, d, w);
+        const int e = a.wk.Rexp[o];
+        const double r = (e == INT_MIN) ? 0.0 : ldexp(a.wk.R64[o], e - K);
+        if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
+        else a.wk.R64[o] = r;
+    }
+}
+
+// derivatives: partial sums over the block's determinants of
+// w_d R_d grad~_e D_d / D_d (row-replacement form, columns of S_d^-1)
+template <int NT>
+__global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a, int sp) {
+    const int w = blockIdx.x, part = blockIdx.y;
+    const size_t ws = (size_t)w * 2 + sp;
+    if (a.wk.flag[ws] == 0) return;
+    const SpinDev S = a.sp[sp];
+    const int M = a.M, N = a.N, tid = threadIdx.x;
+    extern __shared__ double lds[];
+    double *P = lds;                    // [5][NT][M] scaled orbitals and derivatives
+    double *red = P + 5 * NT * M;       // [kDirectBlock / 64][NT * 4]
+    int *Ex = (int *)(red + (kDirectBlock / 64) * NT * 4);  // [M]
+    int *occ0 = Ex + M;                 // [NT]
     const double *phig = a.wk.phi + (size_t)w * N * 5 * M;
+    for (int i = tid; i < 5 * NT * M; i += kDirectBlock) {
+        const int q = i / (NT * M), r = i - q * NT * M, e = r / M, m = r - e * M;
+        P[i] = phig[(size_t)(S.e0 + e) * 5 * M + (size_t)q * M + m];
+    }
+    for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[ws * M + m];
+    for (int c = tid; c < NT; c += kDirectBlock) occ0[c] = S.occ0[c];
+    __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const int K = a.wk.K[ws];
-    const size_t off = (size_t)w * rv_stride(a) + rv_offset(a, sp);
     const bool mixed = a.precision == MDET_MIXED;
-    double acc[4] = {0, 0, 0, 0};
-    for (int d = wave; d < S.U; d += kWaves) {
+    const int d0 = (int)((int64_t)S.U * part / kDirectSplit);
+    const int d1 = (int)((int64_t)S.U * (part + 1) / kDirectSplit);
+    double acc[NT][4];
+#pragma unroll
+    for (int e = 0; e < NT; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[e][q] = 0.0;
+    for (int d = d0 + tid; d < d1; d += kDirectBlock) {
         const DetDesc D = S.desc[d];
         if (D.s > dmax) continue;
+        const size_t o = rv_index(a, sp, d, w);
+        const int rexp = a.wk.Rexp[o];
+        if (rexp == INT_MIN) continue;
+        double A[NT][NT];
+        int perm[NT], occ[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            occ[c] = slot_orbital(D, occ0, c);
+#pragma unroll
+            for (int e = 0; e < NT; ++e) A[e][c] = P[e * M + occ[c]];
+        }
         double mant;
         int ex;
-        wave_lu_det(D, occ0, phig, S.e0, M, n, lane, Sm[wave], piv[wave], occ[wave], mant, ex);
+        lu_regs<NT>(A, perm, mant, ex);
         if (mant == 0.0) continue;
-        int sx = 0;
-        for (int c = 0; c < n; ++c) sx += Ex[occ[wave][c]];
-        const double r = ldexp(mant, ex + sx - K);
-        const double wt = mixed ? (double)a.wk.uv32[off + d] : a.wk.uv64[off + d];
-        double *LUm = Sm[wave];
-        double *Xm = Xw[wave];
-        if (lane < n) {  // column `lane` of S_d^-1
-            const int k = lane;
-            for (int i = 0; i < n; ++i) Xm[i * n + k] = (i == k) ? 1.0 : 0.0;
-            for (int j = 0; j < n; ++j) {
-                const int p = piv[wave][j];
-                if (p != j) {
-                    const double t = Xm[j * n + k];
-                    Xm[j * n + k] = Xm[p * n + k];
-                    Xm[p * n + k] = t;
-                }
+        const double wt = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
+        const double coef = wt * ldexp((double)D.eps * mant, rexp - K);
+        // column e of S_d^-1: solve S x = e_e; grad~_e D_d / D_d = sum_c x_c G_q[e][occ_c]
+#pragma unroll
+        for (int e = 0; e < NT; ++e) {
+            double x[NT];
+#pragma unroll
+            for (int i = 0; i < NT; ++i) x[i] = (perm[i] == e) ? 1.0 : 0.0;
+#pragma unroll
+            for (int i = 0; i < NT; ++i)
+#pragma unroll
+                for (int j = 0; j < i; ++j) x[i] -= A[i][j] * x[j];
+#pragma unroll
+            for (int i = NT - 1; i >= 0; --i) {
+#pragma unroll
+                for (int j = i + 1; j < NT; ++j) x[i] -= A[i][j] * x[j];
+                x[i] /= A[i][i];
             }
-            for (int i = 0; i < n; ++i) {
-                double s = Xm[i * n + k];
-                for (int j = 0; j < i; ++j) s -= LUm[i * n + j] * Xm[j * n + k];
-                Xm[i * n + k] = s;
-            }
-            for (int i = n - 1; i >= 0; --i) {
-                double s = Xm[i * n + k];
-                for (int j = i + 1; j < n; ++j) s -= LUm[i * n + j] * Xm[j * n + k];
-                Xm[i * n + k] = s / LUm[i * n + i];
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (lane < n) {
-            const int e = lane;
+#pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double *G = phig + (size_t)(S.e0 + e) * 5 * M + (size_t)(1 + q) * M;
+                const double *Gq = P + (size_t)(1 + q) * NT * M + e * M;
                 double s = 0.0;
-                for (int c = 0; c < n; ++c) s += Xm[c * n + e] * G[occ[wave][c]];
-                acc[q] += wt * r * s;
+#pragma unroll
+                for (int c = 0; c < NT; ++c) s += x[c] * Gq[occ[c]];
+                acc[e][q] += coef * s;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    if (lane < n)
-        for (int q = 0; q < 4; ++q) part[wave][lane * 4 + q] = acc[q];
+    const int wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int e = 0; e < NT; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double v = wave_sum(acc[e][q]);
+            if (lane == 0) red[wave * NT * 4 + e * 4 + q] = v;
+        }
     __syncthreads();
-    const double psi = mixed ? (double)a.wk.psi32[w] : a.wk.psi64[w];
-    for (int idx = tid; idx < 4 * n; idx += kBlock) {
-        double s = 0.0;
-        for (int v = 0; v < kWaves; ++v) s += part[v][idx];
-        a.gl_out[((size_t)w * N + S.e0) * 4 + idx] = s / psi;
+    for (int i = tid; i < NT * 4; i += kDirectBlock) {
+        double t = 0.0;
+        for (int v = 0; v < kDirectBlock / 64; ++v) t += red[v * NT * 4 + i];
+        a.wk.dpart[(((size_t)w * kDirectSplit + part) * N + S.e0) * 4 + i] = t;
     }
 }
 
 // ---------------------------------------------------------------------------
-// Outputs: sign, ln|Psi|, status; nodes get zero derivatives.
+// Outputs: sign, ln|Psi|, status; the fallback's derivative partials are
+// combined here; nodes get zero derivatives.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a) {
     const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (w >= a.W) return;
-    const bool mixed = a.precision == MDET_MIXED;
-    const double psi = mixed ? (double)a.wk.psi32[w] : a.wk.psi64[w];
+    const double psi = psi_value(a, (int)w);
     const int f0 = a.wk.flag[2 * w], f1 = a.wk.flag[2 * w + 1];
     const bool node = !(psi != 0.0) || !isfinite(psi);
     if (node) {
@@ -760,6 +1061,16 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a) {
         for (int t = 0; t < 4 * a.N; ++t) a.gl_out[w * 4 * a.N + t] = 0.0;
         if (a.wstatus) a.wstatus[w] = MDET_W_NODE;
         return;
+    }
+    for (int sp = 0; sp < 2; ++sp) {
+        if (a.wk.flag[2 * w + sp] == 0) continue;
+        const int e0 = a.sp[sp].e0, n = a.sp[sp].n;
+        for (int t = 4 * e0; t < 4 * (e0 + n); ++t) {
+            double s = 0.0;
+            for (int p = 0; p < kDirectSplit; ++p)
+                s += a.wk.dpart[((size_t)w * kDirectSplit + p) * a.N * 4 + t];
+            a.gl_out[w * 4 * a.N + t] = s / psi;
+        }
     }
     const double sg = a.wk.sign0[2 * w] * a.wk.sign0[2 * w + 1] * (psi > 0 ? 1.0 : -1.0);
     a.sign_out[w] = sg;
@@ -776,9 +1087,58 @@ const char *kernel_name(int k) {
     return (k >= 0 && k < kNumKernels) ? names[k] : "";
 }
 
-hipError_t launch_eval(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
-    const int W = (int)a.W;
+namespace {
+
+template <int NT>
+void launch_direct(const KernelArgs &a, hipStream_t st, int sp, bool deriv) {
+    const int M = a.M, W = (int)a.W;
+    const dim3 grid(W, kDirectSplit);
+    if (deriv) {
+        const size_t lds = sizeof(double) * (5 * (size_t)NT * M + (kDirectBlock / 64) * NT * 4) +
+                           sizeof(int) * (M + NT);
+        k_direct_deriv_t<NT><<<grid, dim3(kDirectBlock), lds, st>>>(a, sp);
+    } else {
+        const size_t lds = sizeof(double) * (size_t)NT * M + sizeof(int) * (M + NT);
+        k_direct_ratios_t<NT><<<grid, dim3(kDirectBlock), lds, st>>>(a, sp);
+    }
+}
+
+void launch_direct_n(const KernelArgs &a, hipStream_t st, bool deriv) {
+    for (int sp = 0; sp < 2; ++sp) {
+        switch (a.sp[sp].n) {
+        case 1: launch_direct<1>(a, st, sp, deriv); break;
+        case 2: launch_direct<2>(a, st, sp, deriv); break;
+        case 3: launch_direct<3>(a, st, sp, deriv); break;
+        case 4: launch_direct<4>(a, st, sp, deriv); break;
+        case 5: launch_direct<5>(a, st, sp, deriv); break;
+        case 6: launch_direct<6>(a, st, sp, deriv); break;
+        case 7: launch_direct<7>(a, st, sp, deriv); break;
+        case 8: launch_direct<8>(a, st, sp, deriv); break;
+        case 9: launch_direct<9>(a, st, sp, deriv); break;
+        case 10: launch_direct<10>(a, st, sp, deriv); break;
+        case 11: launch_direct<11>(a, st, sp, deriv); break;
+        case 12: launch_direct<12>(a, st, sp, deriv); break;
+        case 13: launch_direct<13>(a, st, sp, deriv); break;
+        case 14: launch_direct<14>(a, st, sp, deriv); break;
+        case 15: launch_direct<15>(a, st, sp, deriv); break;
+        default: launch_direct<16>(a, st, sp, deriv); break;  // n <= MDET_MAX_SPIN_ELEC = 16
+        }
+    }
+}
+
+int psi_splits(int64_t W) {
+    const int64_t tiles = (W + kSpmmTile - 1) / kSpmmTile;
+    const int rs = (int)((256 + tiles - 1) / tiles);
+    return std::max(1, std::min(rs, kPsiParts));
+}
+
+}  // namespace
+
+hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
+    const int W = (int)args.W;
     if (W == 0) return hipSuccess;
+    KernelArgs a = args;
+    a.psi_nparts = psi_splits(W);
     const int n = a.nmax, M = a.M;
     const dim3 g2(2 * W), blk(kBlock);
     auto mark = [&](int k) {
@@ -791,20 +1151,25 @@ hipError_t launch_eval(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     size_t lds_rat = sizeof(double) * (size_t)n * M + sizeof(int) * (M + n);
     k_ratios<<<g2, blk, lds_rat, st>>>(a);
     mark(2);
-    k_direct_ratios<<<g2, blk, sizeof(int) * M, st>>>(a);
+    launch_direct_n(a, st, false);
+    k_direct_scale<<<dim3(2 * W, kDirectSplit), blk, 0, st>>>(a);
     mark(3);
+    const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
+    const dim3 gs(tiles * a.psi_nparts, 2), bs(64 * kSpmmWaves);
     if (a.precision == MDET_MIXED)
-        k_spmm<float><<<dim3(W), blk, 0, st>>>(a, a.wk.R32, a.wk.uv32, a.wk.psi32, a.C.rval32,
-                                               a.C.cval32);
+        k_spmm<float, kSpmmCols32, true><<<gs, bs, 0, st>>>(
+            a, a.wk.R32, a.wk.uv32, a.C.rval32, a.C.cval32, a.C.rcol, a.C.crow, a.C.rseg32,
+            a.C.cseg32, a.C.nch_r32, a.C.nch_c32, a.psi_nparts);
     else
-        k_spmm<double><<<dim3(W), blk, 0, st>>>(a, a.wk.R64, a.wk.uv64, a.wk.psi64, a.C.rval,
-                                                a.C.cval);
+        k_spmm<double, kSpmmCols64, false><<<gs, bs, 0, st>>>(
+            a, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
+            a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
     mark(4);
-    size_t lds_der = sizeof(double) * ((size_t)n * M + 2 * n * n + 2 * (size_t)M * n) +
+    size_t lds_der = sizeof(double) * (3 * (size_t)n * M + 2 * n * n + kAdjChunk) +
                      sizeof(int) * (M + n);
     k_deriv<<<g2, blk, lds_der, st>>>(a);
     mark(5);
-    k_direct_deriv<<<g2, blk, sizeof(int) * M, st>>>(a);
+    launch_direct_n(a, st, true);
     mark(6);
     k_finalize<<<dim3((W + kBlock - 1) / kBlock), blk, 0, st>>>(a);
     mark(7);

@@ -29,8 +29,13 @@ def gpu_eval(ev, R, precision=0, max_degree=None):
 
 
 def scaled_errors(ref, sign, logabs, gl, idx=None):
-    """Per-walker scaled errors (psi, grad/lap) of GPU outputs vs the oracle.
-    idx maps oracle rows to GPU rows (default identity)."""
+    """Per-walker scaled errors of the GPU outputs against the oracle.
+
+    Psi:   |sigma sigma* exp(l - l*) - 1| * |Psi*| / S_Psi      (log domain)
+    grad~: |x Psi - x* Psi*| / S_grad = |x sigma sigma* exp(l - l*) - x*| / (S_grad/|Psi*|)
+    i.e. the error of grad~Psi itself (not of the quotient grad~Psi/Psi) over the
+    oracle's sum of the absolute values of its terms, max over electrons and
+    components.  idx maps oracle rows to GPU rows (default identity)."""
     W = ref.sign.shape[0]
     idx = np.arange(W) if idx is None else np.asarray(idx)
     ep = np.zeros(W)
@@ -41,13 +46,21 @@ def scaled_errors(ref, sign, logabs, gl, idx=None):
             ep[r] = 0.0 if sign[w] == 0.0 else np.inf
             eg[r] = 0.0
             continue
-        if sign[w] != ref.sign[r]:
-            # a sign flip is only acceptable when |Psi| is below the noise of the sum
-            ep[r] = (1.0 + math.exp(min(700.0, logabs[w] - ref.logabs[r]))) / ref.rs_psi[r]
-        else:
-            ep[r] = abs(math.expm1(logabs[w] - ref.logabs[r])) / ref.rs_psi[r]
-        eg[r] = np.max(np.abs(gl[w] - ref.gl[r]) / ref.rs_gl[r])
+        f = sign[w] * ref.sign[r] * math.exp(min(700.0, logabs[w] - ref.logabs[r]))
+        ep[r] = abs(f - 1.0) / ref.rs_psi[r]
+        eg[r] = np.max(np.abs(gl[w] * f - ref.gl[r]) / ref.rs_gl[r])
     return ep, eg
+
+
+def ratio_errors(ref, gl, idx=None):
+    """max |x - x*| / (S_grad/|Psi*|) for the quotient x = grad~Psi/Psi."""
+    W = ref.sign.shape[0]
+    idx = np.arange(W) if idx is None else np.asarray(idx)
+    out = np.zeros(W)
+    for r in range(W):
+        if ref.sign[r] != 0.0:
+            out[r] = np.max(np.abs(gl[idx[r]] - ref.gl[r]) / ref.rs_gl[r])
+    return out
 
 
 def rel_errors(ref, gl, idx=None):

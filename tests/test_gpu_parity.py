@@ -7,8 +7,8 @@ import pytest
 
 import oracle
 from gen.workloads import encode, make_config, make_custom
-from parity_util import (FP64_TOL, MIXED_TOL, gpu_eval, log, rel_errors, scaled_errors,
-                         summary)
+from parity_util import (FP64_TOL, MIXED_TOL, gpu_eval, log, ratio_errors, rel_errors,
+                         scaled_errors, summary)
 
 pytestmark = pytest.mark.gpu
 
@@ -64,8 +64,10 @@ def test_mixed_parity_c3():
     ep, eg = scaled_errors(ref, sign, logabs, gl)
     summary("c3 mixed", ep, eg, ws)
     rel = rel_errors(ref, gl)
+    rat = ratio_errors(ref, gl)
     log(f"c3 mixed plain relative grad/lap error p50 {np.median(rel):.2e} "
-        f"p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}")
+        f"p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}; quotient-form scaled error "
+        f"p50 {np.median(rat):.2e} p99 {np.percentile(rat, 99):.2e} max {rat.max():.2e}")
     assert ep.max() <= MIXED_TOL and eg.max() <= MIXED_TOL
 
 
