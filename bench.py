@@ -25,23 +25,24 @@ PEAK_FP32 = 157.3e12     # FP32 vector flop/s
 PEAK_HBM = 8.0e12        # bytes/s
 
 
-def kernel_model(name, wl, st, W, precision):
-    """Algorithmic flops and HBM bytes of one launch of `name` on W walkers.
+def kernel_model(name, wl, st, W, precision, n_fallback=0):
+    """Algorithmic flops and HBM bytes of one launch of kernel `name` on W walkers.
 
-    Counts follow the algorithm (no padding, no recomputation): an FMA is 2
-    flops, an exp is counted as 1 flop.  Bytes are the data a kernel must
-    read or write at least once.
+    Counts follow the algorithm, not the implementation: an FMA is 2 flops,
+    an exp is counted as 1 flop; bytes are what the kernel must read or write
+    at least once (C once per launch, per-walker vectors once).
+    Returns (flops, bytes, arithmetic type of the dominant operations).
     """
     n = (wl.n_up, wl.n_dn)
     M, P, N = wl.n_mo, wl.n_prim, wl.n_up + wl.n_dn
     U, V, Z = st.n_uniq_up, st.n_uniq_dn, st.n_det
     degs = (list(st.n_by_degree_up), list(st.n_by_degree_dn))
     b = 4 if precision == 1 else 8
-    det_flops = {0: 0, 1: 0, 2: 3, 3: 14, 4: 47}
-    cof_flops = {1: 0, 2: 0, 3: 3, 4: 14}
+    det_flops = {0: 0, 1: 0, 2: 3, 3: 2 * 27 // 3, 4: 2 * 64 // 3}     # LU of s x s
+    adj_flops = {1: 0, 2: 0, 3: 2 * 27, 4: 2 * 64}                     # Gauss-Jordan
     if name == "k_spmm":
         flops = W * (4 * Z + 2 * U)
-        byts = 2 * Z * (b + 4) + 4 * (U + V + 2) + W * (U + V) * 2 * b + W * b
+        byts = 2 * Z * (b + 4) + 4 * (U + V + 2) + W * (U + V) * 2 * b + W * 8
         return flops, byts, ("fp32" if b == 4 else "fp64")
     if name == "k_ratios":
         flops = W * sum(sum(c * det_flops[s] for s, c in enumerate(d)) for d in degs)
@@ -50,7 +51,7 @@ def kernel_model(name, wl, st, W, precision):
     if name == "k_deriv":
         f = 0
         for d, nn in zip(degs, n):
-            f += sum(c * s * s * (cof_flops.get(s, 0) + 3) for s, c in enumerate(d) if s > 0)
+            f += sum(c * (adj_flops[s] + 2 * s * s) for s, c in enumerate(d) if s > 0)
             f += 2 * M * nn * nn + 2 * nn * nn * M + 4 * nn * 2 * (M + nn)
         byts = W * (sum(nn * M * 8 + nn * nn * 8 for nn in n) + (U + V) * b + 4 * N * M * 8
                     + N * 4 * 8 * 2)
@@ -58,9 +59,14 @@ def kernel_model(name, wl, st, W, precision):
     if name == "k_reference":
         f = N * M * P * 36
         for nn in n:
-            f += (2 * nn ** 3) // 3 + 2 * nn ** 3 + 4 * nn ** 3 + 2 * nn * nn * M + 8 * nn * nn
-        byts = W * (N * 3 * 8 + 5 * N * M * 8 + 2 * (nn * M * 8))
+            f += 2 * nn ** 3 + 4 * nn ** 3 + 2 * nn * nn * M + 8 * nn * nn
+        byts = W * (N * 3 * 8 + 5 * N * M * 8 + sum(2 * nn * M * 8 for nn in n))
         return W * f, byts, "fp64"
+    if name in ("k_direct_ratios", "k_direct_deriv"):
+        # n_fallback (walker, spin) pairs, one LU per distinct determinant
+        nn = max(n)
+        per = 2 * nn ** 3 // 3 + (2 * nn ** 3 + 8 * nn * nn if name == "k_direct_deriv" else 0)
+        return n_fallback * max(U, V) * per, n_fallback * 5 * nn * M * 8, "fp64"
     return 0, 0, "fp64"
 
 
@@ -139,7 +145,8 @@ def main():
     value = args.steps * W / r["dt"]
     dom = max(r["times"], key=lambda k: r["times"][k])
     avg_ms = r["times"][dom] / max(r["calls"], 1)
-    flops, byts, kdt = kernel_model(dom, wl, r["st"], W, prec)
+    n_fb = int(np.sum(r["ws"] == 1))
+    flops, byts, kdt = kernel_model(dom, wl, r["st"], W, prec, n_fallback=n_fb)
     t = avg_ms * 1e-3
     peak_f = PEAK_FP32 if kdt == "fp32" else PEAK_FP64
     if byts / PEAK_HBM >= flops / peak_f:

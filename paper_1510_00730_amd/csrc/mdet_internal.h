@@ -35,13 +35,13 @@ static_assert(sizeof(DetDesc) == 16, "DetDesc layout");
 
 // Capacity (doubles) of the LDS staging buffer that holds the scaled
 // adjugates of one chunk of determinants during the derivative aggregation.
-constexpr int kAdjChunk = 4096;
+constexpr int kAdjChunk = 2048;
 // Sparse combination: a tile of 64 walkers (one per lane) stages the
 // gathered vector in LDS by chunks of kSpmmCols64 (FP64) or kSpmmCols32
-// (FP32) entries, 128 KB either way.
+// (FP32) entries, 130 KB either way (row pitch 65).
 constexpr int kSpmmTile = 64;
-constexpr int kSpmmCols64 = 256;
-constexpr int kSpmmCols32 = 512;
+constexpr int kSpmmCols64 = 250;
+constexpr int kSpmmCols32 = 500;
 
 // Device view of one spin channel of the expansion.
 struct SpinDev {
@@ -82,7 +82,8 @@ struct Work {
     int64_t W;
     int64_t Wld;       // leading dimension (walkers) of the walker-minor vectors
     int32_t M, N, nmax, Upad, Vpad;
-    double *phi;       // [W][N][5][M] orbitals and derivatives, column-scaled
+    double *phi;       // [W][N][5][M] orbitals and derivatives (unscaled; column m of spin
+                       // sigma is used as phi * 2^-E[sigma][m])
     int32_t *E;        // [W][2][M] per-spin column exponents
     double *X;         // [W][2][nmax*nmax] inverse of the scaled reference
     double *T;         // [W][2][nmax][M] table A^-1 Phi (scaled)
@@ -91,12 +92,12 @@ struct Work {
     double *sign0;     // [W][2]
     int32_t *flag;     // [W][2] 0 table method, 1 ill-conditioned, 2 singular
     int32_t *K;        // [W][2] exponent shift of the ratio vectors
-    double *R64;       // [Upad+Vpad][Wld] walker-minor: R_up rows then R_dn rows
-    float *R32;        // [Upad+Vpad][Wld]
-    double *uv64;      // [Upad+Vpad][Wld] u (up rows) then v (down rows)
-    float *uv32;       // [Upad+Vpad][Wld]
+    double *R64;       // [W][Upad+Vpad] walker-major: R_up then R_dn
+    float *R32;        // [W][Upad+Vpad]
+    double *uv64;      // [W][Upad+Vpad] u (up part) then v (down part)
+    float *uv32;       // [W][Upad+Vpad]
     double *psi64;     // [W][kPsiParts] partial sums of psi (FP64 in both precisions)
-    int32_t *Rexp;     // [Upad+Vpad][Wld] direct-LU fallback: exponents of the determinants
+    int32_t *Rexp;     // [W][Upad+Vpad] direct-LU fallback: exponents of the determinants
     int32_t *Kmax;     // [W][2] direct-LU fallback: largest exponent (integer max)
     double *dpart;     // [W][kDirectSplit][N][4] direct-LU fallback: derivative partial sums
 };

@@ -270,10 +270,10 @@ __device__ __forceinline__ double det_lu(const double *m) {
     return det;
 }
 
-// Offsets of the walker-minor vectors R, u, v: entry d of spin sp for walker w
-// sits at ((sp ? Upad : 0) + d) * Wld + w.
+// Offsets of the walker-major vectors R, u, v: entry d of spin sp for walker
+// w sits at w * (Upad + Vpad) + (sp ? Upad : 0) + d.
 __device__ __forceinline__ size_t rv_index(const KernelArgs &a, int sp, int d, int w) {
-    return ((size_t)(sp ? a.wk.Upad : 0) + d) * (size_t)a.wk.Wld + w;
+    return (size_t)w * (size_t)(a.wk.Upad + a.wk.Vpad) + (sp ? (size_t)a.wk.Upad : 0) + d;
 }
 
 // psi of walker w: the row-split partial sums of the sparse combination
@@ -347,27 +347,91 @@ __device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// K1+K2+K3: orbitals, scaled reference LU, inverse, refinement, table T, g0.
+// K1+K2+K3: orbitals, scaled reference inverse, refinement, table T, g0.
 // One block per (walker, spin).
 // ---------------------------------------------------------------------------
+namespace {
+
+// Gauss-Jordan elimination with partial pivoting of the n x n matrix held one
+// row per lane (lanes 0..n-1 of one wave, n <= kMaxN): on return lane i
+// holds row i of the inverse in x[] and every lane the log|det| and sign.
+// Returns false on an exactly zero pivot.
+__device__ bool wave_gauss_jordan(int n, int lane, double (&r)[kMaxN], double (&x)[kMaxN],
+                                  double &logabs, double &sign) {
+#pragma unroll
+    for (int k = 0; k < kMaxN; ++k) x[k] = (lane == k) ? 1.0 : 0.0;
+    logabs = 0.0;
+    sign = 1.0;
+#pragma unroll
+    for (int j = 0; j < kMaxN; ++j) {
+        if (j >= n) break;
+        double v = (lane >= j && lane < n) ? fabs(r[j]) : -1.0;
+        int id = lane;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double v2 = __shfl_xor(v, off, 64);
+            const int i2 = __shfl_xor(id, off, 64);
+            if (v2 > v || (v2 == v && i2 < id)) {
+                v = v2;
+                id = i2;
+            }
+        }
+        if (!(v > 0.0)) return false;
+        const int src = (lane == j) ? id : ((lane == id) ? j : lane);
+        double pr[kMaxN], px[kMaxN];
+#pragma unroll
+        for (int k = 0; k < kMaxN; ++k) {
+            r[k] = __shfl(r[k], src, 64);
+            x[k] = __shfl(x[k], src, 64);
+        }
+#pragma unroll
+        for (int k = 0; k < kMaxN; ++k) {
+            pr[k] = __shfl(r[k], j, 64);
+            px[k] = __shfl(x[k], j, 64);
+        }
+        const double piv = pr[j];
+        if (id != j) sign = -sign;
+        if (piv < 0.0) sign = -sign;
+        logabs += log(fabs(piv));
+        const double rinv = 1.0 / piv;
+        if (lane == j) {
+#pragma unroll
+            for (int k = 0; k < kMaxN; ++k) {
+                r[k] = pr[k] * rinv;
+                x[k] = px[k] * rinv;
+            }
+        } else {
+            const double f = r[j] * rinv;
+#pragma unroll
+            for (int k = 0; k < kMaxN; ++k) {
+                r[k] -= f * pr[k];
+                x[k] -= f * px[k];
+            }
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
 __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
     const SpinDev S = a.sp[sp];
     const int n = S.n, M = a.M, N = a.N, e0 = S.e0, tid = threadIdx.x;
     extern __shared__ double lds[];
-    double *phi0 = lds;            // [n][M] scaled orbital values
-    double *Aor = phi0 + n * M;    // [n][n] scaled reference
-    double *LU = Aor + n * n;      // [n][n]
-    double *Xs = LU + n * n;       // [n][n]
-    double *Rm = Xs + n * n;       // [n][n]
-    int *Ex = (int *)(Rm + n * n); // [M]
-    __shared__ int piv[kMaxN];
-    __shared__ int s_state;        // 0 ok, 2 singular
+    double *phi0 = lds;             // [n][M] scaled orbital values
+    double *scl = phi0 + n * M;     // [M]    2^-E[m]
+    double *Aor = scl + M;          // [n][n] scaled reference
+    double *Xs = Aor + n * n;       // [n][n]
+    double *Rm = Xs + n * n;        // [n][n]
+    int *Ex = (int *)(Rm + n * n);  // [M]
+    __shared__ int s_state;         // 0 ok, 2 singular
+    __shared__ double s_logabs, s_sign;
     __shared__ double colA[kMaxN], colX[kMaxN];
+    const size_t ws = (size_t)w * 2 + sp;
 
     double *phig = a.wk.phi + (size_t)w * N * 5 * M;
     const double *Rw = a.R + (size_t)w * N * 3;
-
+    // orbitals and derivatives, written once (unscaled)
     for (int idx = tid; idx < n * M; idx += kBlock) {
         const int e = idx / M, m = idx - e * M;
         const double *r = Rw + 3 * (e0 + e);
@@ -377,66 +441,40 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         for (int q = 0; q < 5; ++q) dst[q * M] = o[q];
         phi0[e * M + m] = o[0];
     }
-    if (tid == 0) s_state = 0;
     __syncthreads();
+    // power-of-two column scale of every orbital over this spin's electrons
     for (int m = tid; m < M; m += kBlock) {
         double mx = 0.0;
         for (int e = 0; e < n; ++e) mx = fmax(mx, fabs(phi0[e * M + m]));
         Ex[m] = expo(mx);
-        a.wk.E[((size_t)w * 2 + sp) * M + m] = Ex[m];
+        scl[m] = pow2(-Ex[m]);
+        a.wk.E[ws * M + m] = Ex[m];
     }
     __syncthreads();
-    for (int idx = tid; idx < n * M; idx += kBlock) {
-        const int e = idx / M, m = idx - e * M;
-        const double sc = pow2(-Ex[m]);
-        phi0[idx] *= sc;
-        double *dst = phig + (size_t)(e0 + e) * 5 * M + m;
-        for (int q = 0; q < 5; ++q) dst[q * M] *= sc;
-    }
+    for (int idx = tid; idx < n * M; idx += kBlock) phi0[idx] *= scl[idx % M];
     __syncthreads();
     for (int idx = tid; idx < n * n; idx += kBlock) {
         const int e = idx / n, c = idx - e * n;
-        const double v = phi0[e * M + S.occ0[c]];
-        Aor[idx] = v;
-        LU[idx] = v;
+        Aor[idx] = phi0[e * M + S.occ0[c]];
     }
     __syncthreads();
-    // LU with partial pivoting: lane i of wave 0 scans row i
-    for (int j = 0; j < n; ++j) {
-        if (tid < 64) {
-            double v = (tid >= j && tid < n) ? fabs(LU[tid * n + j]) : -1.0;
-            int id = tid;
-            for (int off = 32; off > 0; off >>= 1) {
-                const double v2 = __shfl_xor(v, off, 64);
-                const int i2 = __shfl_xor(id, off, 64);
-                if (v2 > v || (v2 == v && i2 < id)) {
-                    v = v2;
-                    id = i2;
-                }
-            }
-            if (tid == 0) {
-                piv[j] = id;
-                if (!(v > 0.0)) s_state = 2;
-            }
+    // inverse of the scaled reference by one wave (row per lane)
+    if (tid < 64) {
+        double r[kMaxN], x[kMaxN];
+#pragma unroll
+        for (int k = 0; k < kMaxN; ++k) r[k] = (tid < n && k < n) ? Aor[tid * n + k] : 0.0;
+        double la, sg;
+        const bool ok = wave_gauss_jordan(n, tid, r, x, la, sg);
+        if (ok && tid < n)
+            for (int k = 0; k < n; ++k) Xs[tid * n + k] = x[k];
+        if (tid == 0) {
+            s_state = ok ? 0 : 2;
+            s_logabs = la;
+            s_sign = sg;
         }
-        __syncthreads();
-        if (s_state) break;
-        const int p = piv[j];
-        if (p != j && tid < n) {
-            const double t = LU[j * n + tid];
-            LU[j * n + tid] = LU[p * n + tid];
-            LU[p * n + tid] = t;
-        }
-        __syncthreads();
-        if (tid > j && tid < n) {
-            const double l = LU[tid * n + j] / LU[j * n + j];
-            LU[tid * n + j] = l;
-            for (int c = j + 1; c < n; ++c) LU[tid * n + c] -= l * LU[j * n + c];
-        }
-        __syncthreads();
     }
-    const size_t ws = (size_t)w * 2 + sp;
     if (tid == 0) a.wk.Kmax[ws] = INT_MIN;
+    __syncthreads();
     if (s_state) {
         if (tid == 0) {
             a.wk.flag[ws] = 2;
@@ -445,59 +483,33 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         }
         return;
     }
-    // inverse: thread k solves A x = e_k using the factors
-    if (tid < n) {
-        const int k = tid;
-        for (int i = 0; i < n; ++i) Xs[i * n + k] = (i == k) ? 1.0 : 0.0;
-        for (int j = 0; j < n; ++j) {
-            const int p = piv[j];
-            if (p != j) {
-                const double t = Xs[j * n + k];
-                Xs[j * n + k] = Xs[p * n + k];
-                Xs[p * n + k] = t;
-            }
-        }
-        for (int i = 0; i < n; ++i) {
-            double s = Xs[i * n + k];
-            for (int j = 0; j < i; ++j) s -= LU[i * n + j] * Xs[j * n + k];
-            Xs[i * n + k] = s;
-        }
-        for (int i = n - 1; i >= 0; --i) {
-            double s = Xs[i * n + k];
-            for (int j = i + 1; j < n; ++j) s -= LU[i * n + j] * Xs[j * n + k];
-            Xs[i * n + k] = s / LU[i * n + i];
-        }
-    }
     if (tid == 0) {
-        double la = 0.0, sg = 1.0;
-        for (int j = 0; j < n; ++j) {
-            const double d = LU[j * n + j];
-            la += log(fabs(d));
-            if (d < 0) sg = -sg;
-            if (piv[j] != j) sg = -sg;
-        }
         int sx = 0;
         for (int c = 0; c < n; ++c) sx += Ex[S.occ0[c]];
-        a.wk.logdet0[ws] = la + (double)sx * 0.69314718055994530942;
-        a.wk.sign0[ws] = sg;
+        a.wk.logdet0[ws] = s_logabs + (double)sx * 0.69314718055994530942;
+        a.wk.sign0[ws] = s_sign;
     }
-    __syncthreads();
     // one residual-correction step: X <- X + X (I - A X)
     for (int idx = tid; idx < n * n; idx += kBlock) {
         const int i = idx / n, j = idx - i * n;
-        double s = (i == j) ? 1.0 : 0.0;
-        for (int k = 0; k < n; ++k) s -= Aor[i * n + k] * Xs[k * n + j];
-        Rm[idx] = s;
+        double t = (i == j) ? 1.0 : 0.0;
+        for (int k = 0; k < n; ++k) t -= Aor[i * n + k] * Xs[k * n + j];
+        Rm[idx] = t;
     }
     __syncthreads();
+    double xr[4];
+    int nx = 0;
     for (int idx = tid; idx < n * n; idx += kBlock) {
         const int i = idx / n, j = idx - i * n;
-        double s = Xs[idx];
-        for (int k = 0; k < n; ++k) s += Xs[i * n + k] * Rm[k * n + j];
-        LU[idx] = s;  // refined inverse
+        double t = Xs[idx];
+        for (int k = 0; k < n; ++k) t += Xs[i * n + k] * Rm[k * n + j];
+        xr[nx++] = t;
     }
     __syncthreads();
-    double *X = LU;
+    nx = 0;
+    for (int idx = tid; idx < n * n; idx += kBlock) Xs[idx] = xr[nx++];
+    __syncthreads();
+    const double *X = Xs;
     if (tid < n) {
         double ca = 0.0, cx = 0.0;
         for (int i = 0; i < n; ++i) {
@@ -509,12 +521,12 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     }
     __syncthreads();
     if (tid == 0) {
-        double na = 0.0, nx = 0.0;
+        double na = 0.0, nxm = 0.0;
         for (int c = 0; c < n; ++c) {
             na = fmax(na, colA[c]);
-            nx = fmax(nx, colX[c]);
+            nxm = fmax(nxm, colX[c]);
         }
-        const double kappa = na * nx;
+        const double kappa = na * nxm;
         a.wk.flag[ws] = (kappa <= a.kappa_max) ? 0 : 1;  // NaN -> fallback
     }
     double *Xg = a.wk.X + ws * a.nmax * a.nmax;
@@ -522,16 +534,16 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     double *Tg = a.wk.T + ws * a.nmax * M;
     for (int idx = tid; idx < n * M; idx += kBlock) {
         const int c = idx / M, m = idx - c * M;
-        double s = 0.0;
-        for (int e = 0; e < n; ++e) s += X[c * n + e] * phi0[e * M + m];
-        Tg[idx] = s;
+        double t = 0.0;
+        for (int e = 0; e < n; ++e) t += X[c * n + e] * phi0[e * M + m];
+        Tg[idx] = t;
     }
     for (int idx = tid; idx < 4 * n; idx += kBlock) {
         const int e = idx >> 2, q = idx & 3;
         const double *g = phig + (size_t)(e0 + e) * 5 * M + (size_t)(1 + q) * M;
-        double s = 0.0;
-        for (int c = 0; c < n; ++c) s += X[c * n + e] * g[S.occ0[c]];
-        a.wk.g0[((size_t)w * N + e0 + e) * 4 + q] = s;
+        double t = 0.0;
+        for (int c = 0; c < n; ++c) t += X[c * n + e] * (g[S.occ0[c]] * scl[S.occ0[c]]);
+        a.wk.g0[((size_t)w * N + e0 + e) * 4 + q] = t;
     }
 }
 
@@ -591,6 +603,7 @@ __global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
 // grid.y = pass.
 // ---------------------------------------------------------------------------
 constexpr int kSpmmWaves = 16;
+constexpr int kSpmmLd = kSpmmTile + 1;  // LDS row pitch of the staged vector
 
 // s + x with the rounding error of the addition carried in comp (TwoSum)
 template <typename F>
@@ -609,7 +622,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
            const int32_t *__restrict__ rcol, const int32_t *__restrict__ crow,
            const int32_t *__restrict__ rseg, const int32_t *__restrict__ cseg, int nch_r, int nch_c,
            int rsplit) {
-    __shared__ F G[CC * kSpmmTile];
+    __shared__ F G[CC * kSpmmLd];
     __shared__ double red[kSpmmWaves][kSpmmTile];
     const int pass = blockIdx.y;
     const int tile = blockIdx.x / rsplit, rs = blockIdx.x - tile * rsplit;
@@ -624,7 +637,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
     const int32_t *__restrict__ idx = pass ? crow : rcol;
     const int32_t *__restrict__ seg = pass ? cseg : rseg;
     const F *__restrict__ val = pass ? cval : rval;
-    const size_t Wld = (size_t)a.wk.Wld;
+    const size_t RV = (size_t)a.wk.Upad + a.wk.Vpad;
     const size_t goff = pass ? 0 : (size_t)a.wk.Upad;   // gathered: R_up (pass 1) / R_dn (pass 0)
     const size_t ooff = pass ? (size_t)a.wk.Upad : 0;   // written: v / u
     const int r0 = (int)((int64_t)nrows * rs / rsplit), r1 = (int)((int64_t)nrows * (rs + 1) / rsplit);
@@ -633,14 +646,17 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
         const int cb = c * CC;
         const int nc = min(CC, ncols - cb);
         __syncthreads();
+        // walker-major source: consecutive threads read consecutive entries of
+        // one walker; the LDS row pitch kSpmmLd = 65 keeps both the stores here
+        // and the lane-contiguous reads below free of bank conflicts
         for (int t = threadIdx.x; t < nc * kSpmmTile; t += 64 * kSpmmWaves) {
-            const int jj = t >> 6, ww = t & 63;
-            G[t] = (w0 + ww < W) ? R[(goff + cb + jj) * Wld + w0 + ww] : (F)0;
+            const int ww = t / nc, jj = t - ww * nc;
+            G[jj * kSpmmLd + ww] = (w0 + ww < W) ? R[(size_t)(w0 + ww) * RV + goff + cb + jj] : (F)0;
         }
         __syncthreads();
         for (int i = r0 + wave; i < r1; i += kSpmmWaves) {
             const int kb = seg[(size_t)c * nrows + i], ke = seg[(size_t)(c + 1) * nrows + i];
-            const size_t o = (ooff + i) * Wld + w;
+            const size_t o = (size_t)w * RV + ooff + i;
             F s = (c == 0 || !active) ? (F)0 : uv[o];
             // 8 nonzeros per step: their scalar loads and LDS reads are all in
             // flight before the first multiply-add; two independent sums
@@ -655,7 +671,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                     vx[t] = val[k + t];
                 }
 #pragma unroll
-                for (int t = 0; t < 8; ++t) gx[t] = G[((jx[t] - cb) << 6) + lane];
+                for (int t = 0; t < 8; ++t) gx[t] = G[(jx[t] - cb) * kSpmmLd + lane];
 #pragma unroll
                 for (int t = 0; t < 8; t += 2) {
                     if constexpr (COMP) {
@@ -668,7 +684,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                 }
             }
             for (; k < ke; ++k) {
-                const F x = val[k] * G[((idx[k] - cb) << 6) + lane];
+                const F x = val[k] * G[(idx[k] - cb) * kSpmmLd + lane];
                 if constexpr (COMP) two_sum_acc(s, comp, x);
                 else s += x;
             }
@@ -679,7 +695,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                 s += s2;
             }
             if (active) uv[o] = s;
-            if (pass == 0 && c == nch - 1 && active) part += (double)R[(size_t)i * Wld + w] * (double)s;
+            if (pass == 0 && c == nch - 1 && active) part += (double)R[(size_t)w * RV + i] * (double)s;
         }
     }
     if (pass == 0) {
@@ -777,8 +793,8 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
         const int e = idx >> 2, q = idx & 3;
         const double *Gq = phig + (size_t)(S.e0 + e) * 5 * M + (size_t)(1 + q) * M;
         double s1 = 0.0, s2 = 0.0;
-        for (int m = 0; m < M; ++m) s1 += Gq[m] * Y[m * n + e];
-        for (int c = 0; c < n; ++c) s2 += Gq[occ0[c]] * Zc[c * n + e];
+        for (int m = 0; m < M; ++m) s1 += (Gq[m] * pow2(-Ex[m])) * Y[m * n + e];
+        for (int c = 0; c < n; ++c) s2 += (Gq[occ0[c]] * pow2(-Ex[occ0[c]])) * Zc[c * n + e];
         const size_t o = ((size_t)w * N + S.e0 + e) * 4 + q;
         a.gl_out[o] = a.wk.g0[o] + (s1 - s2) / psi;
     }
@@ -879,12 +895,13 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_ratios_t(KernelArgs a, 
     int *occ0 = Ex + M;               // [NT]
     __shared__ int red[kDirectBlock];
     const double *phig = a.wk.phi + (size_t)w * a.N * 5 * M;
-    for (int i = tid; i < NT * M; i += kDirectBlock) {
-        const int e = i / M, m = i - e * M;
-        P0[i] = phig[(size_t)(S.e0 + e) * 5 * M + m];
-    }
     for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[ws * M + m];
     for (int c = tid; c < NT; c += kDirectBlock) occ0[c] = S.occ0[c];
+    __syncthreads();
+    for (int i = tid; i < NT * M; i += kDirectBlock) {
+        const int e = i / M, m = i - e * M;
+        P0[i] = phig[(size_t)(S.e0 + e) * 5 * M + m] * pow2(-Ex[m]);
+    }
     __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const int d0 = (int)((int64_t)S.U * part / kDirectSplit);
@@ -966,12 +983,13 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a, i
     int *Ex = (int *)(red + (kDirectBlock / 64) * NT * 4);  // [M]
     int *occ0 = Ex + M;                 // [NT]
     const double *phig = a.wk.phi + (size_t)w * N * 5 * M;
-    for (int i = tid; i < 5 * NT * M; i += kDirectBlock) {
-        const int q = i / (NT * M), r = i - q * NT * M, e = r / M, m = r - e * M;
-        P[i] = phig[(size_t)(S.e0 + e) * 5 * M + (size_t)q * M + m];
-    }
     for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[ws * M + m];
     for (int c = tid; c < NT; c += kDirectBlock) occ0[c] = S.occ0[c];
+    __syncthreads();
+    for (int i = tid; i < 5 * NT * M; i += kDirectBlock) {
+        const int q = i / (NT * M), r = i - q * NT * M, e = r / M, m = r - e * M;
+        P[i] = phig[(size_t)(S.e0 + e) * 5 * M + (size_t)q * M + m] * pow2(-Ex[m]);
+    }
     __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const int K = a.wk.K[ws];
@@ -1145,7 +1163,7 @@ hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
-    size_t lds_ref = sizeof(double) * ((size_t)n * M + 4 * n * n) + sizeof(int) * M;
+    size_t lds_ref = sizeof(double) * ((size_t)n * M + M + 3 * n * n) + sizeof(int) * M;
     k_reference<<<g2, blk, lds_ref, st>>>(a);
     mark(1);
     size_t lds_rat = sizeof(double) * (size_t)n * M + sizeof(int) * (M + n);
