@@ -210,3 +210,19 @@ def walker_pool(wl: Workload, n_pool: int, seed: int = 7, sigma: float = 2.0) ->
     """Extra walker sets of the same distribution (rotated per timed step)."""
     rng = np.random.default_rng(np.random.SeedSequence(seed))
     return rng.normal(0.0, sigma, size=(n_pool,) + wl.R.shape)
+
+
+def mlp_init(n_in: int, n_hid: int, n_out: int, seed: int = 0, out_scale: float = 0.05) -> np.ndarray:
+    """Initial parameters of the proposal network (flat FP32, layout
+    [W1, b1, W2, b2, W3, b3]): uniform +-1/sqrt(fan_in) hidden layers, a small
+    output layer, zero biases except the log-step bias (ln 0.3, a modest
+    initial step)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    W1 = rng.uniform(-1, 1, (n_in, n_hid)) / math.sqrt(n_in)
+    W2 = rng.uniform(-1, 1, (n_hid, n_hid)) / math.sqrt(n_hid)
+    W3 = rng.uniform(-1, 1, (n_hid, n_out)) * out_scale / math.sqrt(n_hid)
+    b3 = np.zeros(n_out)
+    n_e = n_out // 4
+    b3[3 * n_e:] = math.log(0.3)
+    parts = [W1, np.zeros(n_hid), W2, np.zeros(n_hid), W3, b3]
+    return np.concatenate([p.ravel() for p in parts]).astype(np.float32)

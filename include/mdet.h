@@ -194,6 +194,88 @@ mdet_status mdet_set_profiling(mdet_ctx *ctx, int32_t enable);
 mdet_status mdet_get_kernel_times(mdet_ctx *ctx, int32_t capacity, double *ms_total,
                                   const char **names, int32_t *n_kernels, int64_t *n_calls);
 
+/* ------------------------------------------------------------------------
+ * Variational Monte Carlo and the learned proposal.  A Monte Carlo step
+ * moves all electrons of a walker and computes Psi, its derivatives and the
+ * local energy (the step of Sec. 4).
+ * ------------------------------------------------------------------------ */
+
+enum { MDET_PROP_GAUSSIAN = 0, MDET_PROP_DRIFT = 1, MDET_PROP_MLP = 2 };
+enum { MDET_RNG_UNIFORM = 0, MDET_RNG_NORMAL = 1 };
+
+/*
+ * Philox-4x32-10 counter-based random numbers (Salmon et al., SC'11).
+ * Element pair i is drawn from counter (i, stream_id, step_lo, step_hi) under
+ * key (seed_lo, seed_hi); its 4 outputs give two doubles in (0,1) from 52 bits
+ * each, u = (x0 2^20 + (x1 >> 12) + 1/2) 2^-52, returned as is (kind
+ * MDET_RNG_UNIFORM) or through Box-Muller (MDET_RNG_NORMAL).  out_dev: double
+ * [n], device.  Asynchronous on hip_stream.
+ */
+mdet_status mdet_rng_fill(mdet_ctx *ctx, uint64_t seed, uint64_t stream_id, uint64_t step,
+                          int64_t n, int32_t kind, double *out_dev, void *hip_stream);
+
+/*
+ * One VMC step for n_walk walkers (all device pointers, updated in place):
+ *  proposal  MDET_PROP_GAUSSIAN: R' = R + step xi;  MDET_PROP_DRIFT:
+ *            R' = R + step grad ln|Psi(R)| + sqrt(step) xi;  MDET_PROP_MLP:
+ *            R' = R + mu(R) + sigma(R) xi with the network of mdet_mlp_forward
+ *            (mlp_params, n_hidden; inputs the 3N coordinates, outputs the 3N
+ *            move means and N log steps clamped to [ln 0.01, ln 2]).
+ *  Acceptance: u < |Psi(R')/Psi(R)|^2 q(R|R')/q(R'|R) (exact Metropolis-
+ *            Hastings, computed in logs; never onto a node of Psi).
+ *  R_dev [W][N][3], sign/logabs [W], gl [W][N][4]: walker state, consistent on
+ *            entry (from mdet_eval_walkers) and on exit.
+ *  noise_dev [W][N][3] standard normals, uniform_dev [W] in (0,1) (e.g. from
+ *            mdet_rng_fill).
+ *  elocal_dev [W]: E_L = -1/2 sum_e lap_e Psi/Psi - Z sum_e 1/|r_e|
+ *            + sum_{e<f} 1/|r_e - r_f| at the walker's position after the
+ *            step (Z = nuclear_charge at the origin); accepted_dev [W]: 0/1.
+ */
+mdet_status mdet_vmc_step(mdet_ctx *ctx, int64_t n_walk, int32_t proposal, double step,
+                          const float *mlp_params, int32_t n_hidden, double *R_dev,
+                          double *sign_dev, double *logabs_dev, double *gl_dev,
+                          const double *noise_dev, const double *uniform_dev,
+                          double nuclear_charge, int32_t precision, double *elocal_dev,
+                          int32_t *accepted_dev, void *hip_stream);
+
+/*
+ * The proposal network, FP32, on device: x -> tanh(x W1 + b1) -> tanh(. W2 +
+ * b2) -> . W3 + b3.  params: [W1 (n_in x n_hidden), b1, W2 (n_hidden x
+ * n_hidden), b2, W3 (n_hidden x n_out), b3], row-major, contiguous.
+ * X [batch][n_in] -> Y [batch][n_out].  The dense layers run on the matrix
+ * cores.
+ */
+mdet_status mdet_mlp_forward(mdet_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                             const float *params, int64_t batch, const float *X, float *Y,
+                             void *hip_stream);
+
+/* Gradient of sum(dY * Y(X)) w.r.t. the parameters (dparams, same layout,
+ * overwritten) and, if dX is not null, w.r.t. the inputs. */
+mdet_status mdet_mlp_backward(mdet_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                              const float *params, int64_t batch, const float *X, const float *dY,
+                              float *dparams, float *dX, void *hip_stream);
+
+/* One bias-corrected Adam step (t = 1-based step count) on n parameters. */
+mdet_status mdet_mlp_adam(mdet_ctx *ctx, int64_t n, float *params, const float *grads, float *m,
+                          float *v, int32_t t, float lr, float beta1, float beta2, float eps,
+                          void *hip_stream);
+
+/*
+ * One training step of the proposal network on walker samples R_dev
+ * [W][N][3] with move noise noise_dev [W][N][3]: maximises the expected
+ * squared jump distance with the exact acceptance,
+ *   loss = -mean_w A_w |R'_w - R_w|^2,  R' = R + mu(R) + sigma(R) xi,
+ *   A = min(1, |Psi(R')/Psi(R)|^2 q(R|R')/q(R'|R)),
+ * differentiating through both network evaluations, through ln|Psi(R')|
+ * (grad ln|Psi| from the multideterminant path) and through q; then one Adam
+ * step (beta 0.9/0.999, eps 1e-8).  loss_dev: double [1]; grad_dev: float
+ * [n_params] or null (gradient before the update).
+ */
+mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden, float *params,
+                                float *adam_m, float *adam_v, int32_t t, float lr,
+                                const double *R_dev, const double *noise_dev, int32_t precision,
+                                double *loss_dev, float *grad_dev, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,10 @@ STATUS = {0: "MDET_OK", -1: "MDET_EINVAL", -2: "MDET_EDIM", -3: "MDET_EPOPCOUNT"
 EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbitals",
             "mdet_set_expansion", "mdet_get_indexing", "mdet_eval_walkers",
             "mdet_set_fallback_threshold", "mdet_get_stats", "mdet_set_profiling",
-            "mdet_get_kernel_times"]
+            "mdet_get_kernel_times", "mdet_rng_fill", "mdet_vmc_step", "mdet_mlp_forward",
+            "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step"]
+PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
+RNG_UNIFORM, RNG_NORMAL = 0, 1
 
 
 class MdetError(RuntimeError):
@@ -65,6 +68,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_get_stats": (I32, [P, P]),
         "mdet_set_profiling": (I32, [P, I32]),
         "mdet_get_kernel_times": (I32, [P, I32, P, P, P, P]),
+        "mdet_rng_fill": (I32, [P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, I64, I32, P, P]),
+        "mdet_vmc_step": (I32, [P, I64, I32, D, P, I32, P, P, P, P, P, P, D, I32, P, P, P]),
+        "mdet_mlp_forward": (I32, [P, I32, I32, I32, P, I64, P, P, P]),
+        "mdet_mlp_backward": (I32, [P, I32, I32, I32, P, I64, P, P, P, P, P]),
+        "mdet_mlp_adam": (I32, [P, I64, P, P, P, P, I32, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float, P]),
+        "mdet_mlp_train_step": (I32, [P, I64, I32, P, P, P, I32, ctypes.c_float, P, P, I32, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -211,3 +221,56 @@ class Evaluator:
         self.eval_raw(W, _dptr(R), precision, _dptr(max_degree), _dptr(sign), _dptr(logabs),
                       _dptr(gl), _dptr(ws), ctypes.c_void_p(stream.cuda_stream))
         return out
+
+    # -------------------------------------------------------------- VMC / MLP
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = torch.cuda.current_stream() if stream is None else stream
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def rng_fill(self, out, seed, stream_id, step, kind=RNG_NORMAL, stream=None):
+        """Fill the float64 device tensor `out` with Philox uniforms or normals."""
+        self._check(_LIB.mdet_rng_fill(self._h, int(seed), int(stream_id), int(step), out.numel(),
+                                       int(kind), _dptr(out), self._stream(stream)))
+        return out
+
+    def vmc_step(self, R, sign, logabs, gl, noise, uniform, elocal, accepted, proposal=PROP_GAUSSIAN,
+                 step=0.3, mlp_params=None, n_hidden=0, nuclear_charge=None, precision=MDET_FP64,
+                 stream=None):
+        """One VMC step on device tensors, in place (see mdet_vmc_step)."""
+        Z = float(self.n_up + self.n_dn) if nuclear_charge is None else float(nuclear_charge)
+        self._check(_LIB.mdet_vmc_step(self._h, R.shape[0], int(proposal), float(step),
+                                       _dptr(mlp_params), int(n_hidden), _dptr(R), _dptr(sign),
+                                       _dptr(logabs), _dptr(gl), _dptr(noise), _dptr(uniform), Z,
+                                       int(precision), _dptr(elocal), _dptr(accepted),
+                                       self._stream(stream)))
+
+    def mlp_forward(self, params, X, n_hidden, n_out, Y=None, stream=None):
+        import torch
+        Y = torch.empty((X.shape[0], n_out), dtype=torch.float32, device=X.device) if Y is None else Y
+        self._check(_LIB.mdet_mlp_forward(self._h, X.shape[1], int(n_hidden), int(n_out),
+                                          _dptr(params), X.shape[0], _dptr(X), _dptr(Y),
+                                          self._stream(stream)))
+        return Y
+
+    def mlp_backward(self, params, X, dY, n_hidden, want_dX=True, stream=None):
+        import torch
+        dp = torch.empty_like(params)
+        dX = torch.empty_like(X) if want_dX else None
+        self._check(_LIB.mdet_mlp_backward(self._h, X.shape[1], int(n_hidden), dY.shape[1],
+                                           _dptr(params), X.shape[0], _dptr(X), _dptr(dY), _dptr(dp),
+                                           _dptr(dX), self._stream(stream)))
+        return dp, dX
+
+    def mlp_adam(self, params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, stream=None):
+        self._check(_LIB.mdet_mlp_adam(self._h, params.numel(), _dptr(params), _dptr(grads), _dptr(m),
+                                       _dptr(v), int(t), float(lr), float(b1), float(b2), float(eps),
+                                       self._stream(stream)))
+
+    def mlp_train_step(self, params, m, v, t, lr, R, noise, n_hidden, loss, grad=None,
+                       precision=MDET_FP64, stream=None):
+        self._check(_LIB.mdet_mlp_train_step(self._h, R.shape[0], int(n_hidden), _dptr(params),
+                                             _dptr(m), _dptr(v), int(t), float(lr), _dptr(R),
+                                             _dptr(noise), int(precision), _dptr(loss), _dptr(grad),
+                                             self._stream(stream)))

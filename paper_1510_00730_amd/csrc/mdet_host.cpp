@@ -138,6 +138,21 @@ struct mdet_ctx {
     DevBuf w_phi, w_E, w_X, w_T, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
         w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart;
     Work wk{};
+    // VMC / MLP work buffers (grow-only)
+    int64_t vcap = 0;
+    MlpShape mshape{0, 0, 0};
+    DevBuf v_Rp, v_signp, v_logabsp, v_glp, v_wsp, v_signR, v_logabsR, v_glR, v_wsR;
+    DevBuf m_X, m_Xp, m_h1a, m_h2a, m_h1b, m_h2b, m_O1, m_O2, m_wh1, m_wh2, m_dO1, m_dO2, m_dX2,
+        m_gRp, m_gell, m_Jw, m_grad;
+
+    void drop_vmc() {
+        for (DevBuf *b : {&v_Rp, &v_signp, &v_logabsp, &v_glp, &v_wsp, &v_signR, &v_logabsR, &v_glR,
+                          &v_wsR, &m_X, &m_Xp, &m_h1a, &m_h2a, &m_h1b, &m_h2b, &m_O1, &m_O2,
+                          &m_wh1, &m_wh2, &m_dO1, &m_dO2, &m_dX2, &m_gRp, &m_gell, &m_Jw, &m_grad})
+            b->release();
+        vcap = 0;
+        mshape = MlpShape{0, 0, 0};
+    }
 
     void drop_expansion() {
         have_exp = false;
@@ -150,6 +165,7 @@ struct mdet_ctx {
             s.d_gpos.release();
             s = SpinHost();
         }
+        drop_vmc();
         for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_rseg, &d_cptr, &d_crow, &d_cval,
                           &d_cval32, &d_cseg, &d_rseg32, &d_cseg32})
             b->release();
@@ -442,9 +458,114 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     c->wcap = W;
 }
 
+// Queue one evaluation (all kernels) on `st`; arguments already validated.
+void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
+                  const int8_t *max_degree_dev, double *sign_dev, double *logabs_dev,
+                  double *gl_dev, int32_t *wstatus_dev, hipStream_t st) {
+    ensure_work(ctx, n_walk);
+    KernelArgs a{};
+    a.n_up = ctx->n_up;
+    a.n_dn = ctx->n_dn;
+    a.N = ctx->n_up + ctx->n_dn;
+    a.M = ctx->n_mo;
+    a.P = ctx->n_prim;
+    a.nmax = std::max(ctx->n_up, ctx->n_dn);
+    a.kappa_max = ctx->kappa_max;
+    a.prim = ctx->d_prim.as<Prim>();
+    for (int s = 0; s < 2; ++s) {
+        SpinDev &d = a.sp[s];
+        d.n = ctx->sp[s].n;
+        d.e0 = s == 0 ? 0 : ctx->n_up;
+        d.U = (int32_t)ctx->sp[s].U;
+        d.nchunk = (int32_t)ctx->sp[s].chunk_det.size() - 1;
+        d.occ0 = ctx->sp[s].d_occ0.as<int32_t>();
+        d.desc = ctx->sp[s].d_desc.as<DetDesc>();
+        d.adj_off = ctx->sp[s].d_adj_off.as<int32_t>();
+        d.chunk_det = ctx->sp[s].d_chunk_det.as<int32_t>();
+        d.gptr = ctx->sp[s].d_gptr.as<int32_t>();
+        d.gpos = ctx->sp[s].d_gpos.as<uint16_t>();
+    }
+    a.C.U = (int32_t)ctx->sp[0].U;
+    a.C.V = (int32_t)ctx->sp[1].U;
+    a.C.Z = ctx->n_det;
+    a.C.rptr = ctx->d_rptr.as<int32_t>();
+    a.C.rcol = ctx->d_rcol.as<int32_t>();
+    a.C.rval = ctx->d_rval.as<double>();
+    a.C.rval32 = ctx->d_rval32.as<float>();
+    a.C.cptr = ctx->d_cptr.as<int32_t>();
+    a.C.crow = ctx->d_crow.as<int32_t>();
+    a.C.cval = ctx->d_cval.as<double>();
+    a.C.cval32 = ctx->d_cval32.as<float>();
+    a.C.rseg64 = ctx->d_rseg.as<int32_t>();
+    a.C.cseg64 = ctx->d_cseg.as<int32_t>();
+    a.C.rseg32 = ctx->d_rseg32.as<int32_t>();
+    a.C.cseg32 = ctx->d_cseg32.as<int32_t>();
+    a.C.nch_r64 = ctx->nch_r;
+    a.C.nch_c64 = ctx->nch_c;
+    a.C.nch_r32 = ctx->nch_r32;
+    a.C.nch_c32 = ctx->nch_c32;
+    a.wk = ctx->wk;
+    a.W = n_walk;
+    a.R = R_dev;
+    a.max_degree = max_degree_dev;
+    a.precision = precision;
+    a.sign_out = sign_dev;
+    a.logabs_out = logabs_dev;
+    a.gl_out = gl_dev;
+    a.wstatus = wstatus_dev;
+    hipEvent_t *ev = ctx->profiling ? ctx->next_event_set() : nullptr;
+    HIP_OK(launch_eval(a, st, ev));
+}
+
+template <typename T>
+T *grow(DevBuf &b, int64_t count) {
+    const size_t need = sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+    if (b.bytes < need) b.alloc(need);
+    return b.as<T>();
+}
+
+// VMC / MLP buffers for W walkers and an MLP of hidden width H
+void ensure_vmc(mdet_ctx *c, int64_t W, int H) {
+    const int N = c->n_up + c->n_dn;
+    const MlpShape sh{3 * N, H, 4 * N};
+    if (W <= c->vcap && sh.n_hid == c->mshape.n_hid) return;
+    const int64_t Wc = std::max(W, c->vcap);
+    grow<double>(c->v_Rp, Wc * N * 3);
+    grow<double>(c->v_signp, Wc);
+    grow<double>(c->v_logabsp, Wc);
+    grow<double>(c->v_glp, Wc * N * 4);
+    grow<int32_t>(c->v_wsp, Wc);
+    grow<double>(c->v_signR, Wc);
+    grow<double>(c->v_logabsR, Wc);
+    grow<double>(c->v_glR, Wc * N * 4);
+    grow<int32_t>(c->v_wsR, Wc);
+    if (H > 0) {
+        grow<float>(c->m_X, Wc * sh.n_in);
+        grow<float>(c->m_Xp, Wc * sh.n_in);
+        grow<float>(c->m_h1a, Wc * H);
+        grow<float>(c->m_h2a, Wc * H);
+        grow<float>(c->m_h1b, Wc * H);
+        grow<float>(c->m_h2b, Wc * H);
+        grow<float>(c->m_O1, Wc * sh.n_out);
+        grow<float>(c->m_O2, Wc * sh.n_out);
+        grow<float>(c->m_wh1, Wc * H);
+        grow<float>(c->m_wh2, Wc * H);
+        grow<float>(c->m_dO1, Wc * sh.n_out);
+        grow<float>(c->m_dO2, Wc * sh.n_out);
+        grow<float>(c->m_dX2, Wc * sh.n_in);
+        grow<double>(c->m_gRp, Wc * sh.n_in);
+        grow<double>(c->m_gell, Wc);
+        grow<double>(c->m_Jw, Wc);
+        grow<float>(c->m_grad, sh.n_params());
+        c->mshape = sh;
+    }
+    c->vcap = Wc;
+}
+
 }  // namespace
 
 extern "C" {
+
 
 mdet_status mdet_create(mdet_ctx **out, int32_t hip_device) {
     if (!out) return MDET_EINVAL;
@@ -476,6 +597,7 @@ void mdet_destroy(mdet_ctx *ctx) {
     }
     ctx->drop_expansion();
     ctx->d_prim.release();
+    ctx->drop_vmc();
     ctx->drop_profile_events();
     delete ctx;
 }
@@ -697,59 +819,8 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
         if (n_walk == 0) return;
         require(R_dev && sign_dev && logabs_dev && gl_dev, MDET_EINVAL, "null output pointer");
         HIP_OK(hipSetDevice(ctx->device));
-        ensure_work(ctx, n_walk);
-        KernelArgs a{};
-        a.n_up = ctx->n_up;
-        a.n_dn = ctx->n_dn;
-        a.N = ctx->n_up + ctx->n_dn;
-        a.M = ctx->n_mo;
-        a.P = ctx->n_prim;
-        a.nmax = std::max(ctx->n_up, ctx->n_dn);
-        a.kappa_max = ctx->kappa_max;
-        a.prim = ctx->d_prim.as<Prim>();
-        for (int s = 0; s < 2; ++s) {
-            SpinDev &d = a.sp[s];
-            d.n = ctx->sp[s].n;
-            d.e0 = s == 0 ? 0 : ctx->n_up;
-            d.U = (int32_t)ctx->sp[s].U;
-            d.nchunk = (int32_t)ctx->sp[s].chunk_det.size() - 1;
-            d.occ0 = ctx->sp[s].d_occ0.as<int32_t>();
-            d.desc = ctx->sp[s].d_desc.as<DetDesc>();
-            d.adj_off = ctx->sp[s].d_adj_off.as<int32_t>();
-            d.chunk_det = ctx->sp[s].d_chunk_det.as<int32_t>();
-            d.gptr = ctx->sp[s].d_gptr.as<int32_t>();
-            d.gpos = ctx->sp[s].d_gpos.as<uint16_t>();
-        }
-        a.C.U = (int32_t)ctx->sp[0].U;
-        a.C.V = (int32_t)ctx->sp[1].U;
-        a.C.Z = ctx->n_det;
-        a.C.rptr = ctx->d_rptr.as<int32_t>();
-        a.C.rcol = ctx->d_rcol.as<int32_t>();
-        a.C.rval = ctx->d_rval.as<double>();
-        a.C.rval32 = ctx->d_rval32.as<float>();
-        a.C.cptr = ctx->d_cptr.as<int32_t>();
-        a.C.crow = ctx->d_crow.as<int32_t>();
-        a.C.cval = ctx->d_cval.as<double>();
-        a.C.cval32 = ctx->d_cval32.as<float>();
-        a.C.rseg64 = ctx->d_rseg.as<int32_t>();
-        a.C.cseg64 = ctx->d_cseg.as<int32_t>();
-        a.C.rseg32 = ctx->d_rseg32.as<int32_t>();
-        a.C.cseg32 = ctx->d_cseg32.as<int32_t>();
-        a.C.nch_r64 = ctx->nch_r;
-        a.C.nch_c64 = ctx->nch_c;
-        a.C.nch_r32 = ctx->nch_r32;
-        a.C.nch_c32 = ctx->nch_c32;
-        a.wk = ctx->wk;
-        a.W = n_walk;
-        a.R = R_dev;
-        a.max_degree = max_degree_dev;
-        a.precision = precision;
-        a.sign_out = sign_dev;
-        a.logabs_out = logabs_dev;
-        a.gl_out = gl_dev;
-        a.wstatus = wstatus_dev;
-        hipEvent_t *ev = ctx->profiling ? ctx->next_event_set() : nullptr;
-        HIP_OK(launch_eval(a, static_cast<hipStream_t>(hip_stream), ev));
+        enqueue_eval(ctx, n_walk, R_dev, precision, max_degree_dev, sign_dev, logabs_dev, gl_dev,
+                     wstatus_dev, static_cast<hipStream_t>(hip_stream));
     });
 }
 
@@ -812,6 +883,176 @@ mdet_status mdet_get_stats(const mdet_ctx *cctx, mdet_stats *out) {
         out->workspace_bytes = ctx->work_bytes();
         out->expansion_bytes = ctx->exp_bytes();
         out->preprocess_seconds = ctx->prep_seconds;
+    });
+}
+
+mdet_status mdet_rng_fill(mdet_ctx *ctx, uint64_t seed, uint64_t stream_id, uint64_t step,
+                          int64_t n, int32_t kind, double *out_dev, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(n >= 0 && (kind == 0 || kind == 1), MDET_EINVAL, "bad size or kind");
+        if (n == 0) return;
+        require(out_dev != nullptr, MDET_EINVAL, "null output");
+        HIP_OK(hipSetDevice(ctx->device));
+        launch_philox(seed, stream_id, step, n, kind, out_dev, static_cast<hipStream_t>(hip_stream));
+        HIP_OK(hipGetLastError());
+    });
+}
+
+mdet_status mdet_vmc_step(mdet_ctx *ctx, int64_t n_walk, int32_t proposal, double step,
+                          const float *mlp_params, int32_t n_hidden, double *R_dev,
+                          double *sign_dev, double *logabs_dev, double *gl_dev,
+                          const double *noise_dev, const double *uniform_dev,
+                          double nuclear_charge, int32_t precision, double *elocal_dev,
+                          int32_t *accepted_dev, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
+        require(proposal >= 0 && proposal <= 2, MDET_EINVAL, "unknown proposal");
+        require(proposal == 2 || step > 0.0, MDET_EINVAL, "step must be positive");
+        require(proposal != 2 || (mlp_params && n_hidden >= 1 && n_hidden <= 4096), MDET_EINVAL,
+                "MLP proposal needs parameters and 1 <= n_hidden <= 4096");
+        require(precision == MDET_FP64 || precision == MDET_MIXED, MDET_EINVAL, "unknown precision");
+        require(n_walk >= 0 && n_walk <= (int64_t)1 << 24, MDET_EDIM, "n_walk out of range");
+        if (n_walk == 0) return;
+        require(R_dev && sign_dev && logabs_dev && gl_dev && noise_dev && uniform_dev &&
+                    elocal_dev && accepted_dev,
+                MDET_EINVAL, "null pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int N = ctx->n_up + ctx->n_dn;
+        ensure_vmc(ctx, n_walk, proposal == 2 ? n_hidden : 0);
+        double *Rp = ctx->v_Rp.as<double>();
+        const float *o1 = nullptr, *o2 = nullptr;
+        const MlpShape sh{3 * N, n_hidden, 4 * N};
+        if (proposal == 2) {
+            launch_to_f32(n_walk * 3 * N, R_dev, ctx->m_X.as<float>(), st);
+            launch_mlp_forward(sh, mlp_params, n_walk, ctx->m_X.as<float>(), ctx->m_h1a.as<float>(),
+                               ctx->m_h2a.as<float>(), ctx->m_O1.as<float>(), st);
+            launch_mlp_propose(n_walk, N, R_dev, ctx->m_O1.as<float>(), noise_dev, Rp, st);
+        } else {
+            launch_vmc_propose(n_walk, N, proposal, step, R_dev, gl_dev, noise_dev, Rp, st);
+        }
+        enqueue_eval(ctx, n_walk, Rp, precision, nullptr, ctx->v_signp.as<double>(),
+                     ctx->v_logabsp.as<double>(), ctx->v_glp.as<double>(), ctx->v_wsp.as<int32_t>(), st);
+        if (proposal == 2) {
+            launch_to_f32(n_walk * 3 * N, Rp, ctx->m_Xp.as<float>(), st);
+            launch_mlp_forward(sh, mlp_params, n_walk, ctx->m_Xp.as<float>(), ctx->m_h1b.as<float>(),
+                               ctx->m_h2b.as<float>(), ctx->m_O2.as<float>(), st);
+            o1 = ctx->m_O1.as<float>();
+            o2 = ctx->m_O2.as<float>();
+        }
+        launch_vmc_accept(n_walk, N, proposal, step, nuclear_charge, R_dev, sign_dev, logabs_dev,
+                          gl_dev, Rp, ctx->v_signp.as<double>(), ctx->v_logabsp.as<double>(),
+                          ctx->v_glp.as<double>(), uniform_dev, o1, o2, elocal_dev, accepted_dev, st);
+        HIP_OK(hipGetLastError());
+    });
+}
+
+mdet_status mdet_mlp_forward(mdet_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                             const float *params, int64_t batch, const float *X, float *Y,
+                             void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(n_in >= 1 && n_hidden >= 1 && n_out >= 1 && batch >= 0, MDET_EINVAL, "bad shape");
+        if (batch == 0) return;
+        require(params && X && Y, MDET_EINVAL, "null pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        float *h1 = grow<float>(ctx->m_h1a, batch * n_hidden);
+        float *h2 = grow<float>(ctx->m_h2a, batch * n_hidden);
+        launch_mlp_forward(MlpShape{n_in, n_hidden, n_out}, params, batch, X, h1, h2, Y, st);
+        HIP_OK(hipGetLastError());
+    });
+}
+
+mdet_status mdet_mlp_backward(mdet_ctx *ctx, int32_t n_in, int32_t n_hidden, int32_t n_out,
+                              const float *params, int64_t batch, const float *X, const float *dY,
+                              float *dparams, float *dX, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(n_in >= 1 && n_hidden >= 1 && n_out >= 1 && batch >= 1, MDET_EINVAL, "bad shape");
+        require(params && X && dY && dparams, MDET_EINVAL, "null pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const MlpShape sh{n_in, n_hidden, n_out};
+        float *h1 = grow<float>(ctx->m_h1a, batch * n_hidden);
+        float *h2 = grow<float>(ctx->m_h2a, batch * n_hidden);
+        float *O = grow<float>(ctx->m_O1, batch * n_out);
+        float *w1 = grow<float>(ctx->m_wh1, batch * n_hidden);
+        float *w2 = grow<float>(ctx->m_wh2, batch * n_hidden);
+        launch_mlp_forward(sh, params, batch, X, h1, h2, O, st);
+        launch_mlp_backward(sh, params, batch, X, h1, h2, dY, dparams, 0, dX, w1, w2, st);
+        HIP_OK(hipGetLastError());
+    });
+}
+
+mdet_status mdet_mlp_adam(mdet_ctx *ctx, int64_t n, float *params, const float *grads, float *m,
+                          float *v, int32_t t, float lr, float beta1, float beta2, float eps,
+                          void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(n >= 0 && t >= 1 && lr > 0.f && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f &&
+                    beta2 < 1.f && eps > 0.f,
+                MDET_EINVAL, "bad Adam arguments");
+        if (n == 0) return;
+        require(params && grads && m && v, MDET_EINVAL, "null pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        launch_adam(n, params, grads, m, v, lr, beta1, beta2, eps, t,
+                    static_cast<hipStream_t>(hip_stream));
+        HIP_OK(hipGetLastError());
+    });
+}
+
+mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden, float *params,
+                                float *adam_m, float *adam_v, int32_t t, float lr,
+                                const double *R_dev, const double *noise_dev, int32_t precision,
+                                double *loss_dev, float *grad_dev, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
+        require(n_walk >= 1 && n_walk <= (int64_t)1 << 24 && n_hidden >= 1 && n_hidden <= 4096,
+                MDET_EDIM, "bad batch or width");
+        require(t >= 1 && lr > 0.f, MDET_EINVAL, "bad step count or learning rate");
+        require(precision == MDET_FP64 || precision == MDET_MIXED, MDET_EINVAL, "unknown precision");
+        require(params && adam_m && adam_v && R_dev && noise_dev && loss_dev, MDET_EINVAL,
+                "null pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int N = ctx->n_up + ctx->n_dn;
+        const MlpShape sh{3 * N, n_hidden, 4 * N};
+        ensure_vmc(ctx, n_walk, n_hidden);
+        double *Rp = ctx->v_Rp.as<double>();
+        float *grad = grad_dev ? grad_dev : ctx->m_grad.as<float>();
+        // ln|Psi(R)|, the network at R, the proposal, Psi and the network at R'
+        enqueue_eval(ctx, n_walk, R_dev, precision, nullptr, ctx->v_signR.as<double>(),
+                     ctx->v_logabsR.as<double>(), ctx->v_glR.as<double>(), ctx->v_wsR.as<int32_t>(), st);
+        launch_to_f32(n_walk * 3 * N, R_dev, ctx->m_X.as<float>(), st);
+        launch_mlp_forward(sh, params, n_walk, ctx->m_X.as<float>(), ctx->m_h1a.as<float>(),
+                           ctx->m_h2a.as<float>(), ctx->m_O1.as<float>(), st);
+        launch_mlp_propose(n_walk, N, R_dev, ctx->m_O1.as<float>(), noise_dev, Rp, st);
+        enqueue_eval(ctx, n_walk, Rp, precision, nullptr, ctx->v_signp.as<double>(),
+                     ctx->v_logabsp.as<double>(), ctx->v_glp.as<double>(), ctx->v_wsp.as<int32_t>(), st);
+        launch_to_f32(n_walk * 3 * N, Rp, ctx->m_Xp.as<float>(), st);
+        launch_mlp_forward(sh, params, n_walk, ctx->m_Xp.as<float>(), ctx->m_h1b.as<float>(),
+                           ctx->m_h2b.as<float>(), ctx->m_O2.as<float>(), st);
+        // loss and gradient: through the second evaluation, then the first
+        launch_esjd_head(n_walk, N, R_dev, Rp, noise_dev, ctx->v_logabsR.as<double>(),
+                         ctx->v_signp.as<double>(), ctx->v_logabsp.as<double>(),
+                         ctx->v_glp.as<double>(), ctx->m_O1.as<float>(), ctx->m_O2.as<float>(),
+                         ctx->m_dO2.as<float>(), ctx->m_gRp.as<double>(), ctx->m_gell.as<double>(),
+                         ctx->m_Jw.as<double>(), st);
+        launch_mlp_backward(sh, params, n_walk, ctx->m_Xp.as<float>(), ctx->m_h1b.as<float>(),
+                            ctx->m_h2b.as<float>(), ctx->m_dO2.as<float>(), grad, 0,
+                            ctx->m_dX2.as<float>(), ctx->m_wh1.as<float>(), ctx->m_wh2.as<float>(), st);
+        launch_esjd_chain(n_walk, N, noise_dev, ctx->m_O1.as<float>(), ctx->m_gRp.as<double>(),
+                          ctx->m_dX2.as<float>(), ctx->m_gell.as<double>(), ctx->m_dO1.as<float>(), st);
+        launch_mlp_backward(sh, params, n_walk, ctx->m_X.as<float>(), ctx->m_h1a.as<float>(),
+                            ctx->m_h2a.as<float>(), ctx->m_dO1.as<float>(), grad, 1, nullptr,
+                            ctx->m_wh1.as<float>(), ctx->m_wh2.as<float>(), st);
+        launch_esjd_loss(n_walk, ctx->m_Jw.as<double>(), loss_dev, st);
+        launch_adam(sh.n_params(), params, grad, adam_m, adam_v, lr, 0.9f, 0.999f, 1e-8f, t, st);
+        HIP_OK(hipGetLastError());
     });
 }
 

@@ -133,4 +133,47 @@ const char *kernel_name(int k);
 // stream before the first kernel and after each kernel.
 hipError_t launch_eval(const KernelArgs &a, hipStream_t stream, hipEvent_t *events);
 
+// ---------------------------------------------------------------- VMC and MLP
+constexpr double kMlpLogSigMin = -4.6051701859880914;  // ln 0.01
+constexpr double kMlpLogSigMax = 0.69314718055994531;  // ln 2
+
+struct MlpShape {
+    int n_in, n_hid, n_out;
+    int64_t n_params() const {
+        return (int64_t)n_in * n_hid + n_hid + (int64_t)n_hid * n_hid + n_hid +
+               (int64_t)n_hid * n_out + n_out;
+    }
+};
+
+void launch_philox(uint64_t seed, uint64_t stream_id, uint64_t step, int64_t n, int kind,
+                   double *out, hipStream_t st);
+void launch_vmc_propose(int64_t W, int N, int proposal, double step, const double *R,
+                        const double *gl, const double *xi, double *Rp, hipStream_t st);
+void launch_vmc_accept(int64_t W, int N, int proposal, double step, double Z, double *R,
+                       double *sign, double *logabs, double *gl, const double *Rp,
+                       const double *signp, const double *logabsp, const double *glp,
+                       const double *uniform, const float *o1, const float *o2, double *elocal,
+                       int32_t *accepted, hipStream_t st);
+void launch_gemm_f32(int M, int Nn, int K, const float *A, int a_rs, int a_cs, const float *B,
+                     int b_rs, int b_cs, float *C, int c_rs, const float *bias, int act,
+                     int accumulate, hipStream_t st);
+void launch_mlp_forward(const MlpShape &s, const float *params, int64_t B, const float *X,
+                        float *h1, float *h2, float *O, hipStream_t st);
+void launch_mlp_backward(const MlpShape &s, const float *params, int64_t B, const float *X,
+                         const float *h1, const float *h2, const float *dO, float *dparams,
+                         int accumulate, float *dX, float *work_h1, float *work_h2,
+                         hipStream_t st);
+void launch_to_f32(int64_t n, const double *x, float *y, hipStream_t st);
+void launch_mlp_propose(int64_t W, int N, const double *R, const float *o, const double *xi,
+                        double *Rp, hipStream_t st);
+void launch_esjd_head(int64_t W, int N, const double *R, const double *Rp, const double *xi,
+                      const double *logabsR, const double *signp, const double *logabsp,
+                      const double *glp, const float *o1, const float *o2, float *dO2,
+                      double *gRp, double *gell, double *Jw, hipStream_t st);
+void launch_esjd_chain(int64_t W, int N, const double *xi, const float *o1, const double *gRp,
+                       const float *dX2, const double *gell, float *dO1, hipStream_t st);
+void launch_esjd_loss(int64_t W, const double *Jw, double *out, hipStream_t st);
+void launch_adam(int64_t n, float *p, const float *g, float *m, float *v, float lr, float b1,
+                 float b2, float eps, int t, hipStream_t st);
+
 }  // namespace mdet

@@ -1,0 +1,197 @@
+"""GPU parity of the VMC step and the learned proposal against the FP64
+references in oracle/ (rng, mlp, vmc), through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from oracle import rng as orng
+from oracle import vmc as ovmc
+from gen.workloads import make_config, mlp_init
+from parity_util import log
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+import paper_1510_00730_amd as mdet  # noqa: E402
+from paper_1510_00730_amd import binding as B  # noqa: E402
+from paper_1510_00730_amd import vmc as V  # noqa: E402
+
+
+def dev(x, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device="cuda")
+
+
+@pytest.fixture(scope="module")
+def c2():
+    wl = make_config(2)
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    return wl, ev
+
+
+def test_philox_matches_reference(c2):
+    log("[vmc] philox")
+    _, ev = c2
+    out = torch.empty(10001, dtype=torch.float64, device="cuda")
+    ev.rng_fill(out, 12345, 7, 3, B.RNG_UNIFORM)
+    u = out.cpu().numpy()
+    assert u.tobytes() == orng.uniforms(12345, 7, 3, 10001).tobytes()
+    ev.rng_fill(out, 2 ** 40 + 5, 1, 2 ** 33 + 1, B.RNG_NORMAL)
+    z = out.cpu().numpy()
+    np.testing.assert_allclose(z, orng.normals(2 ** 40 + 5, 1, 2 ** 33 + 1, 10001), rtol=0, atol=1e-13)
+
+
+def test_mlp_forward_backward_adam(c2):
+    log("[vmc] mlp forward/backward/adam")
+    _, ev = c2
+    n_in, H, n_out, Bn = 51, 128, 68, 300
+    p = mlp_init(n_in, H, n_out, seed=3, out_scale=1.0)
+    rng = np.random.default_rng(4)
+    X = rng.normal(0, 2.0, (Bn, n_in)).astype(np.float32)
+    dY = rng.normal(size=(Bn, n_out)).astype(np.float32)
+    Y = ev.mlp_forward(dev(p, torch.float32), dev(X, torch.float32), H, n_out)
+    ref, cache = omlp.forward(p.astype(np.float64), X.astype(np.float64), H, n_out)
+    np.testing.assert_allclose(Y.cpu().numpy(), ref, rtol=0, atol=2e-5 * np.abs(ref).max())
+    gp, gX = ev.mlp_backward(dev(p, torch.float32), dev(X, torch.float32), dev(dY, torch.float32), H)
+    rgp, rgX = omlp.backward(p.astype(np.float64), cache, dY.astype(np.float64), H, n_out)
+    gp, gX = gp.cpu().numpy(), gX.cpu().numpy()
+    assert np.linalg.norm(gp - rgp) < 2e-5 * np.linalg.norm(rgp)
+    assert np.linalg.norm(gX - rgX) < 2e-5 * np.linalg.norm(rgX)
+    # Adam, two steps
+    pt, m, v = dev(p, torch.float32), torch.zeros(p.size, device="cuda"), torch.zeros(p.size, device="cuda")
+    rp, rm, rv = p.astype(np.float64), np.zeros(p.size), np.zeros(p.size)
+    for t in (1, 2):
+        ev.mlp_adam(pt, dev(rgp, torch.float32), m, v, t, 1e-3)
+        rp, rm, rv = omlp.adam(rp, rgp.astype(np.float32).astype(np.float64), rm, rv, t, 1e-3)
+    np.testing.assert_allclose(pt.cpu().numpy(), rp, rtol=0, atol=1e-6)
+
+
+def _state(ev, R):
+    s, l, g, _ = ev.eval_walkers(dev(R))
+    return s, l, g
+
+
+@pytest.mark.parametrize("proposal,step", [(B.PROP_GAUSSIAN, 0.3), (B.PROP_DRIFT, 0.05)])
+def test_vmc_step_matches_reference(c2, proposal, step):
+    log(f"[vmc] step proposal {proposal}")
+    wl, ev = c2
+    W, N = 64, wl.n_elec
+    R = wl.R[:W].copy()
+    rng = np.random.default_rng(9)
+    xi = rng.normal(size=(W, N, 3))
+    u = rng.random(W)
+    sign, logabs, gl = _state(ev, R)
+    Rt = dev(R)
+    el = torch.empty(W, dtype=torch.float64, device="cuda")
+    acc = torch.empty(W, dtype=torch.int32, device="cuda")
+    gl0 = gl.cpu().numpy()
+    ev.vmc_step(Rt, sign, logabs, gl, dev(xi), dev(u), el, acc, proposal=proposal, step=step,
+                nuclear_charge=N)
+    torch.cuda.synchronize()
+    # reference step from the oracle's own evaluations
+    ref0 = oracle.evaluate(wl, R, n_threads=16)
+    Rp = ovmc.propose(R, ref0.gl, xi, proposal, step)
+    ref1 = oracle.evaluate(wl, Rp, n_threads=16)
+    ell = ovmc.log_accept(R, Rp, ref0.logabs, ref1.logabs, ref0.gl, ref1.gl, proposal, step)
+    ok = (np.log(u) < ell) & (ref1.sign != 0)
+    margin = np.abs(np.log(u) - ell)
+    clear = margin > 1e-6
+    got = acc.cpu().numpy().astype(bool)
+    assert np.array_equal(got[clear], ok[clear])
+    Rnew = np.where(got[:, None, None], Rp, R)
+    np.testing.assert_allclose(Rt.cpu().numpy(), Rnew, rtol=0, atol=1e-12)
+    glnew = np.where(got[:, None, None], ref1.gl, ref0.gl)
+    el_ref = ovmc.local_energy(Rnew, glnew, N)
+    np.testing.assert_allclose(el.cpu().numpy(), el_ref, rtol=1e-8, atol=1e-8)
+    log(f"acceptance {got.mean():.3f}")
+
+
+def test_mlp_vmc_step_matches_reference(c2):
+    log("[vmc] MLP proposal step")
+    wl, ev = c2
+    W, N, H = 64, wl.n_elec, 32
+    p = mlp_init(3 * N, H, 4 * N, seed=11)
+    R = wl.R[:W].copy()
+    rng = np.random.default_rng(10)
+    xi = rng.normal(size=(W, N, 3))
+    u = rng.random(W)
+    sign, logabs, gl = _state(ev, R)
+    Rt = dev(R)
+    el = torch.empty(W, dtype=torch.float64, device="cuda")
+    acc = torch.empty(W, dtype=torch.int32, device="cuda")
+    ev.vmc_step(Rt, sign, logabs, gl, dev(xi), dev(u), el, acc, proposal=B.PROP_MLP,
+                mlp_params=dev(p, torch.float32), n_hidden=H)
+    torch.cuda.synchronize()
+    pd = p.astype(np.float64)
+    o1, _ = omlp.forward(pd, R.reshape(W, -1).astype(np.float32).astype(np.float64), H, 4 * N)
+    mu, ls, _ = omlp.head(o1, N)
+    Rp = R + mu + np.exp(ls)[:, :, None] * xi
+    o2, _ = omlp.forward(pd, Rp.reshape(W, -1).astype(np.float32).astype(np.float64), H, 4 * N)
+    mu2, ls2, _ = omlp.head(o2, N)
+    r0 = oracle.evaluate(wl, R, n_threads=16)
+    r1 = oracle.evaluate(wl, Rp, n_threads=16)
+    ell = (2 * (r1.logabs - r0.logabs) + omlp.log_q(R, Rp, mu2, ls2) - omlp.log_q(Rp, R, mu, ls))
+    ok = np.log(u) < ell
+    clear = np.abs(np.log(u) - ell) > 1e-3
+    got = acc.cpu().numpy().astype(bool)
+    assert np.array_equal(got[clear], ok[clear])
+    Rnew = np.where(got[:, None, None], Rp, R)
+    np.testing.assert_allclose(Rt.cpu().numpy()[clear], Rnew[clear], rtol=0, atol=1e-5)
+
+
+def test_training_step_gradient_matches_reference(c2):
+    """Loss and parameter gradient of the ESJD objective vs the exact FP64 one
+    (which the CPU tests pin by finite differences)."""
+    log("[vmc] MLP training step gradient")
+    wl, ev = c2
+    W, N, H = 64, wl.n_elec, 32
+    p = mlp_init(3 * N, H, 4 * N, seed=12)
+    R = wl.R[:W].copy()
+    xi = np.random.default_rng(13).normal(size=(W, N, 3))
+    pt = dev(p, torch.float32)
+    m = torch.zeros_like(pt)
+    v = torch.zeros_like(pt)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    grad = torch.empty_like(pt)
+    ev.mlp_train_step(pt, m, v, 1, 1e-6, dev(R), dev(xi), H, loss, grad=grad)
+    torch.cuda.synchronize()
+
+    def psi_fn(Rp):
+        r = oracle.evaluate(wl, Rp, n_threads=16)
+        return r.logabs, r.gl[:, :, :3]
+    lR = oracle.evaluate(wl, R, n_threads=16).logabs
+    # the network sees FP32 inputs on the device
+    rl, rg, info = omlp.esjd_loss_and_grad(p.astype(np.float64), R, xi, lR, psi_fn, H)
+    g = grad.cpu().numpy()
+    log(f"loss gpu {float(loss):.6e} ref {rl:.6e}; |g-gref|/|gref| "
+        f"{np.linalg.norm(g - rg) / np.linalg.norm(rg):.2e}; min |ell| {np.abs(info['ell']).min():.2e}")
+    assert abs(float(loss) - rl) < 1e-4 * abs(rl)
+    assert np.linalg.norm(g - rg) < 2e-3 * np.linalg.norm(rg)
+
+
+def test_mlp_proposal_samples_the_same_distribution(c2):
+    """Exactness: <sum r^2> and <E_L> from MLP-proposal VMC agree with
+    Gaussian-proposal VMC within their error bars (untrained network)."""
+    log("[vmc] exactness of the MLP proposal")
+    wl, ev = c2
+    N, H = wl.n_elec, 32
+    p = dev(mlp_init(3 * N, H, 4 * N, seed=21), torch.float32)
+    R0 = wl.R[:256]
+    stats = {}
+    for name, prop, step, mlp_ in (("gauss", B.PROP_GAUSSIAN, 0.25, None),
+                                   ("mlp", B.PROP_MLP, 0.0, (p, H))):
+        w = V.Walkers(ev, R0, seed=31 if name == "gauss" else 32)
+        V.run(w, 200, prop, step, mlp_, record=False)
+        el, r2, acc, _ = V.run(w, 600, prop, step, mlp_)
+        stats[name] = (r2, el, acc)
+        log(f"{name}: acceptance {acc.mean():.3f}, <sum r^2> {r2.mean():.4f}, <E_L> {np.mean(el):.4f}")
+    for k, idx in (("r2", 0),):
+        a, b = stats["gauss"][idx], stats["mlp"][idx]
+        ea = a.std() * math.sqrt(V.tau_int(a) / a.size)
+        eb = b.std() * math.sqrt(V.tau_int(b) / b.size)
+        assert abs(a.mean() - b.mean()) < 4.0 * math.hypot(ea, eb), (k, a.mean(), b.mean(), ea, eb)
