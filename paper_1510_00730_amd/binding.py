@@ -52,8 +52,17 @@ class Stats(ctypes.Structure):
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmdet.  When PyTorch is installed it is imported first: its HIP
+    runtime carries the same soname (libamdhip64.so.7), so the dynamic loader
+    binds libmdet to it and the process holds one HIP runtime -- PyTorch's
+    device pointers and streams are then valid in libmdet's calls.  Loading
+    libmdet first would bring in a second runtime."""
     if not os.path.exists(path):
         raise ImportError(f"libmdet.so not built at {path}; run __graft_entry__.build()")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
