@@ -276,6 +276,52 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
                                 const double *R_dev, const double *noise_dev, int32_t precision,
                                 double *loss_dev, float *grad_dev, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Launch configuration, captured steps and tuning.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * Launch parameters: spmm_row_splits = row splits per 64-walker tile of the
+ * sparse combination (0 = derived from the batch, 1..16); direct_split =
+ * blocks per (walker, spin) of the direct-LU fallback (1..8); sort_walkers =
+ * with a max_degree array, evaluate the walkers in ascending order of their
+ * maximum degree, so that each tile of the sparse combination touches only
+ * the determinants its walkers reach.  FP64 results are bitwise reproducible
+ * for a fixed configuration (the summation grouping depends on the splits).
+ * Default (0, 4, 1).  Changing it drops captured graphs.
+ */
+mdet_status mdet_set_launch_config(mdet_ctx *ctx, int32_t spmm_row_splits, int32_t direct_split,
+                                   int32_t sort_walkers);
+mdet_status mdet_get_launch_config(const mdet_ctx *ctx, int32_t *spmm_row_splits,
+                                   int32_t *direct_split, int32_t *sort_walkers);
+
+/*
+ * Same contract as mdet_eval_walkers, but the whole step (every kernel) is
+ * captured once into a HIP graph per distinct argument set (n_walk,
+ * precision, every pointer, stream; up to 8 cached, least recently used
+ * evicted) and replayed with one graph launch per call.  Inputs may change
+ * between calls, pointers may not (a new pointer set is captured anew).
+ * A NULL stream is replaced by a blocking stream owned by the context.
+ */
+mdet_status mdet_eval_graph(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
+                            const int8_t *max_degree_dev, double *sign_dev, double *logabs_dev,
+                            double *gl_dev, int32_t *wstatus_dev, void *hip_stream);
+
+typedef struct {
+    int32_t spmm_row_splits, direct_split, sort_walkers, n_candidates;
+    double best_ms;     /* mean time per evaluation of the chosen configuration */
+    double default_ms;  /* the same for the first candidate (auto splits)      */
+} mdet_tune_result;
+
+/*
+ * Time every candidate launch configuration (row splits {auto, 4, 8, 16} x
+ * fallback splits {2, 4, 8} x walker sorting {on, off} when max_degree_dev
+ * is given) on n_rep evaluations of the given walkers, keep the fastest in
+ * the context and report it in *out (nullable).  Synchronous.
+ */
+mdet_status mdet_autotune(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
+                          const int8_t *max_degree_dev, int32_t n_rep, mdet_tune_result *out);
+
 #ifdef __cplusplus
 }
 #endif

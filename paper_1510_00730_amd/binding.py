@@ -29,7 +29,8 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_set_expansion", "mdet_get_indexing", "mdet_eval_walkers",
             "mdet_set_fallback_threshold", "mdet_get_stats", "mdet_set_profiling",
             "mdet_get_kernel_times", "mdet_rng_fill", "mdet_vmc_step", "mdet_mlp_forward",
-            "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step"]
+            "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step", "mdet_set_launch_config",
+            "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune"]
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
 RNG_UNIFORM, RNG_NORMAL = 0, 1
 
@@ -49,6 +50,12 @@ class Stats(ctypes.Structure):
                 ("n_by_degree_dn", ctypes.c_int64 * (MAX_DEGREE + 1)),
                 ("workspace_bytes", ctypes.c_int64), ("expansion_bytes", ctypes.c_int64),
                 ("preprocess_seconds", ctypes.c_double)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("spmm_row_splits", ctypes.c_int32), ("direct_split", ctypes.c_int32),
+                ("sort_walkers", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
 def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
@@ -84,6 +91,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_mlp_adam": (I32, [P, I64, P, P, P, P, I32, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, P]),
         "mdet_mlp_train_step": (I32, [P, I64, I32, P, P, P, I32, ctypes.c_float, P, P, I32, P, P, P]),
+        "mdet_set_launch_config": (I32, [P, I32, I32, I32]),
+        "mdet_get_launch_config": (I32, [P, P, P, P]),
+        "mdet_eval_graph": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
+        "mdet_autotune": (I32, [P, I64, P, I32, P, I32, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -283,3 +294,35 @@ class Evaluator:
                                              _dptr(m), _dptr(v), int(t), float(lr), _dptr(R),
                                              _dptr(noise), int(precision), _dptr(loss), _dptr(grad),
                                              self._stream(stream)))
+
+    # -------------------------------------------------------------- tuning / graphs
+    def set_launch_config(self, spmm_row_splits=0, direct_split=4, sort_walkers=True):
+        self._check(_LIB.mdet_set_launch_config(self._h, int(spmm_row_splits), int(direct_split),
+                                                1 if sort_walkers else 0))
+
+    def launch_config(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(_LIB.mdet_get_launch_config(self._h, ctypes.byref(a), ctypes.byref(b),
+                                                ctypes.byref(c)))
+        return a.value, b.value, bool(c.value)
+
+    def eval_graph(self, R, precision=MDET_FP64, max_degree=None, out=None, stream=None):
+        """Like eval_walkers, replaying a captured HIP graph of the whole step."""
+        import torch
+        W, N = R.shape[0], R.shape[1]
+        if out is None:
+            out = (torch.empty(W, dtype=torch.float64, device=R.device),
+                   torch.empty(W, dtype=torch.float64, device=R.device),
+                   torch.empty((W, N, 4), dtype=torch.float64, device=R.device),
+                   torch.empty(W, dtype=torch.int32, device=R.device))
+        sign, logabs, gl, ws = out
+        st = ctypes.c_void_p(None) if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        self._check(_LIB.mdet_eval_graph(self._h, W, _dptr(R), int(precision), _dptr(max_degree),
+                                         _dptr(sign), _dptr(logabs), _dptr(gl), _dptr(ws), st))
+        return out
+
+    def autotune(self, R, precision=MDET_FP64, max_degree=None, n_rep=10) -> TuneResult:
+        r = TuneResult()
+        self._check(_LIB.mdet_autotune(self._h, R.shape[0], _dptr(R), int(precision),
+                                       _dptr(max_degree), int(n_rep), ctypes.byref(r)))
+        return r

@@ -93,8 +93,25 @@ struct mdet_ctx {
     std::vector<double> val;
     std::vector<int64_t> src_pos;
     DevBuf d_rptr, d_rcol, d_rval, d_rval32, d_rseg, d_cptr, d_crow, d_cval, d_cval32, d_cseg;
-    DevBuf d_rseg32, d_cseg32;
+    DevBuf d_rseg32, d_cseg32, d_rdeg, d_cdeg;
     int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
+    LaunchCfg cfg{0, 4, 1};
+    hipStream_t own_stream = nullptr;
+    // captured evaluations (mdet_eval_graph), keyed by every argument
+    struct GraphEntry {
+        int64_t W;
+        const void *ptr[7];
+        int32_t precision;
+        hipStream_t stream;
+        hipGraphExec_t exec;
+        uint64_t last_use;
+    };
+    std::vector<GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    void drop_graphs() {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        graphs.clear();
+    }
     double prep_seconds = 0.0;
     double kappa_max = 3e4;
     // optional per-kernel timing with HIP events on the caller's stream: a
@@ -136,7 +153,8 @@ struct mdet_ctx {
     // walker work buffers
     int64_t wcap = 0;
     DevBuf w_phi, w_E, w_X, w_T, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
-        w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart;
+        w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart, w_perm, w_Rs, w_mds, w_sign_s, w_logabs_s, w_gl_s,
+        w_ws_s;
     Work wk{};
     // VMC / MLP work buffers (grow-only)
     int64_t vcap = 0;
@@ -167,28 +185,31 @@ struct mdet_ctx {
         }
         drop_vmc();
         for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_rseg, &d_cptr, &d_crow, &d_cval,
-                          &d_cval32, &d_cseg, &d_rseg32, &d_cseg32})
+                          &d_cval32, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             b->release();
         drop_work();
     }
     void drop_work() {
         for (DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag, &w_K,
-                          &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp, &w_Kmax, &w_dpart})
+                          &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp, &w_Kmax, &w_dpart,
+                          &w_perm, &w_Rs, &w_mds, &w_sign_s, &w_logabs_s, &w_gl_s, &w_ws_s})
             b->release();
         wcap = 0;
+        drop_graphs();
     }
     int64_t work_bytes() const {
         int64_t t = 0;
         for (const DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag,
                                 &w_K, &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp,
-                                &w_Kmax, &w_dpart})
+                                &w_Kmax, &w_dpart, &w_perm, &w_Rs, &w_mds, &w_sign_s,
+                                &w_logabs_s, &w_gl_s, &w_ws_s})
             t += (int64_t)b->bytes;
         return t;
     }
     int64_t exp_bytes() const {
         int64_t t = (int64_t)d_prim.bytes;
         for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_rseg, &d_cptr, &d_crow,
-                                &d_cval, &d_cval32, &d_cseg, &d_rseg32, &d_cseg32})
+                                &d_cval, &d_cval32, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             t += (int64_t)b->bytes;
         for (const auto &s : sp)
             t += (int64_t)(s.d_occ0.bytes + s.d_desc.bytes + s.d_adj_off.bytes +
@@ -429,7 +450,14 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     c->w_psi64.alloc(sizeof(double) * W * kPsiParts);
     c->w_Rexp.alloc(sizeof(int32_t) * Wld * RV);
     c->w_Kmax.alloc(sizeof(int32_t) * W * 2);
-    c->w_dpart.alloc(sizeof(double) * W * kDirectSplit * N * 4);
+    c->w_dpart.alloc(sizeof(double) * W * kDirectSplitMax * N * 4);
+    c->w_perm.alloc(sizeof(int32_t) * W);
+    c->w_Rs.alloc(sizeof(double) * W * N * 3);
+    c->w_mds.alloc(W);
+    c->w_sign_s.alloc(sizeof(double) * W);
+    c->w_logabs_s.alloc(sizeof(double) * W);
+    c->w_gl_s.alloc(sizeof(double) * W * N * 4);
+    c->w_ws_s.alloc(sizeof(int32_t) * W);
     Work &k = c->wk;
     k.W = W;
     k.Wld = Wld;
@@ -455,6 +483,13 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     k.Rexp = c->w_Rexp.as<int32_t>();
     k.Kmax = c->w_Kmax.as<int32_t>();
     k.dpart = c->w_dpart.as<double>();
+    k.perm = c->w_perm.as<int32_t>();
+    k.Rs = c->w_Rs.as<double>();
+    k.mds = c->w_mds.as<int8_t>();
+    k.sign_s = c->w_sign_s.as<double>();
+    k.logabs_s = c->w_logabs_s.as<double>();
+    k.gl_s = c->w_gl_s.as<double>();
+    k.ws_s = c->w_ws_s.as<int32_t>();
     c->wcap = W;
 }
 
@@ -478,6 +513,13 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
         d.e0 = s == 0 ? 0 : ctx->n_up;
         d.U = (int32_t)ctx->sp[s].U;
         d.nchunk = (int32_t)ctx->sp[s].chunk_det.size() - 1;
+        {
+            int32_t acc = 0;
+            for (int k = 0; k <= MDET_MAX_DEGREE; ++k) {
+                acc += (int32_t)ctx->sp[s].n_by_degree[k];
+                d.deg_end[k] = acc;
+            }
+        }
         d.occ0 = ctx->sp[s].d_occ0.as<int32_t>();
         d.desc = ctx->sp[s].d_desc.as<DetDesc>();
         d.adj_off = ctx->sp[s].d_adj_off.as<int32_t>();
@@ -504,6 +546,9 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.C.nch_c64 = ctx->nch_c;
     a.C.nch_r32 = ctx->nch_r32;
     a.C.nch_c32 = ctx->nch_c32;
+    a.C.rdeg = ctx->d_rdeg.as<int32_t>();
+    a.C.cdeg = ctx->d_cdeg.as<int32_t>();
+    a.cfg = ctx->cfg;
     a.wk = ctx->wk;
     a.W = n_walk;
     a.R = R_dev;
@@ -597,6 +642,8 @@ void mdet_destroy(mdet_ctx *ctx) {
     }
     ctx->drop_expansion();
     ctx->d_prim.release();
+    ctx->drop_graphs();
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     ctx->drop_vmc();
     ctx->drop_profile_events();
     delete ctx;
@@ -723,6 +770,26 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
         }
         std::vector<float> rval32(rval.begin(), rval.end()), cval32(cval.begin(), cval.end());
 
+        // entries of each CSR row / CSC column whose other determinant has degree <= d
+        constexpr int DD = MDET_MAX_DEGREE + 1;
+        std::vector<int32_t> rdeg((size_t)U * DD), cdeg((size_t)V * DD);
+        {
+            std::vector<int> deg_up(U), deg_dn(V);
+            for (int64_t e = 0; e < U; ++e) deg_up[e] = sp[0].desc[e].s;
+            for (int64_t e = 0; e < V; ++e) deg_dn[e] = sp[1].desc[e].s;
+            for (int64_t i = 0; i < U; ++i)
+                for (int d = 0; d < DD; ++d) {
+                    int32_t k = rptr[i];
+                    while (k < rptr[i + 1] && deg_dn[rcol[k]] <= d) ++k;
+                    rdeg[(size_t)i * DD + d] = k;
+                }
+            for (int64_t j = 0; j < V; ++j)
+                for (int d = 0; d < DD; ++d) {
+                    int32_t k = cptr[j];
+                    while (k < cptr[j + 1] && deg_up[crow[k]] <= d) ++k;
+                    cdeg[(size_t)j * DD + d] = k;
+                }
+        }
         int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
         std::vector<int32_t> rseg = chunk_segments(rptr, rcol, U, V, kSpmmCols64, nch_r);
         std::vector<int32_t> cseg = chunk_segments(cptr, crow, V, U, kSpmmCols64, nch_c);
@@ -749,6 +816,8 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->d_cseg.upload(cseg);
             ctx->d_rseg32.upload(rseg32);
             ctx->d_cseg32.upload(cseg32);
+            ctx->d_rdeg.upload(rdeg);
+            ctx->d_cdeg.upload(cdeg);
         }
         ctx->nch_r = nch_r;
         ctx->nch_c = nch_c;
@@ -1053,6 +1122,172 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
         launch_esjd_loss(n_walk, ctx->m_Jw.as<double>(), loss_dev, st);
         launch_adam(sh.n_params(), params, grad, adam_m, adam_v, lr, 0.9f, 0.999f, 1e-8f, t, st);
         HIP_OK(hipGetLastError());
+    });
+}
+
+mdet_status mdet_set_launch_config(mdet_ctx *ctx, int32_t spmm_row_splits, int32_t direct_split,
+                                   int32_t sort_walkers) {
+    return guarded(ctx, [&] {
+        require(spmm_row_splits >= 0 && spmm_row_splits <= kPsiParts, MDET_EINVAL,
+                "spmm_row_splits must be 0 (auto) .. 16");
+        require(direct_split >= 1 && direct_split <= kDirectSplitMax, MDET_EINVAL,
+                "direct_split must be 1 .. 8");
+        ctx->cfg = LaunchCfg{spmm_row_splits, direct_split, sort_walkers ? 1 : 0};
+        ctx->drop_graphs();
+    });
+}
+
+mdet_status mdet_get_launch_config(const mdet_ctx *cctx, int32_t *spmm_row_splits,
+                                   int32_t *direct_split, int32_t *sort_walkers) {
+    mdet_ctx *ctx = const_cast<mdet_ctx *>(cctx);
+    return guarded(ctx, [&] {
+        if (spmm_row_splits) *spmm_row_splits = ctx->cfg.spmm_rsplit;
+        if (direct_split) *direct_split = ctx->cfg.direct_split;
+        if (sort_walkers) *sort_walkers = ctx->cfg.sort_walkers;
+    });
+}
+
+mdet_status mdet_eval_graph(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
+                            const int8_t *max_degree_dev, double *sign_dev, double *logabs_dev,
+                            double *gl_dev, int32_t *wstatus_dev, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context (hip_device -1) cannot evaluate");
+        require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
+        require(n_walk >= 0 && n_walk <= (int64_t)1 << 30, MDET_EDIM, "n_walk out of range");
+        require(precision == MDET_FP64 || precision == MDET_MIXED, MDET_EINVAL, "unknown precision");
+        if (n_walk == 0) return;
+        require(R_dev && sign_dev && logabs_dev && gl_dev, MDET_EINVAL, "null output pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        if (st == nullptr) {  // the legacy default stream cannot be captured: use a blocking stream of our own
+            if (!ctx->own_stream) HIP_OK(hipStreamCreate(&ctx->own_stream));
+            st = ctx->own_stream;
+        }
+        ensure_work(ctx, n_walk);  // any allocation happens before capture
+        const void *key[7] = {R_dev, max_degree_dev, sign_dev, logabs_dev, gl_dev, wstatus_dev, nullptr};
+        mdet_ctx::GraphEntry *hit = nullptr;
+        for (auto &g : ctx->graphs)
+            if (g.W == n_walk && g.precision == precision && g.stream == st &&
+                std::equal(key, key + 7, g.ptr))
+                hit = &g;
+        if (!hit) {
+            if (ctx->graphs.size() >= 8) {  // evict the least recently used
+                auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                            [](const auto &x, const auto &y) { return x.last_use < y.last_use; });
+                (void)hipGraphExecDestroy(lru->exec);
+                ctx->graphs.erase(lru);
+            }
+            const bool prof = ctx->profiling;
+            ctx->profiling = false;  // no event records inside a graph
+            HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                enqueue_eval(ctx, n_walk, R_dev, precision, max_degree_dev, sign_dev, logabs_dev,
+                             gl_dev, wstatus_dev, st);
+            } catch (...) {
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                ctx->profiling = prof;
+                throw;
+            }
+            ctx->profiling = prof;
+            hipGraph_t graph = nullptr;
+            HIP_OK(hipStreamEndCapture(st, &graph));
+            hipGraphExec_t exec = nullptr;
+            const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIP_OK(e);
+            mdet_ctx::GraphEntry ge{};
+            ge.W = n_walk;
+            std::copy(key, key + 7, ge.ptr);
+            ge.precision = precision;
+            ge.stream = st;
+            ge.exec = exec;
+            ctx->graphs.push_back(ge);
+            hit = &ctx->graphs.back();
+        }
+        hit->last_use = ++ctx->graph_clock;
+        HIP_OK(hipGraphLaunch(hit->exec, st));
+    });
+}
+
+mdet_status mdet_autotune(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
+                          const int8_t *max_degree_dev, int32_t n_rep, mdet_tune_result *out) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
+        require(n_walk >= 1 && R_dev && n_rep >= 1 && n_rep <= 1000, MDET_EINVAL, "bad arguments");
+        require(precision == MDET_FP64 || precision == MDET_MIXED, MDET_EINVAL, "unknown precision");
+        HIP_OK(hipSetDevice(ctx->device));
+        const int N = ctx->n_up + ctx->n_dn;
+        DevBuf sg, la, gl, ws;
+        sg.alloc(sizeof(double) * n_walk);
+        la.alloc(sizeof(double) * n_walk);
+        gl.alloc(sizeof(double) * n_walk * N * 4);
+        ws.alloc(sizeof(int32_t) * n_walk);
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        const LaunchCfg saved = ctx->cfg;
+        const bool prof = ctx->profiling;
+        ctx->profiling = false;
+        auto cleanup = [&] {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (st) (void)hipStreamDestroy(st);
+            sg.release();
+            la.release();
+            gl.release();
+            ws.release();
+            ctx->profiling = prof;
+        };
+        try {
+            HIP_OK(hipStreamCreate(&st));
+            HIP_OK(hipEventCreate(&e0));
+            HIP_OK(hipEventCreate(&e1));
+            std::vector<LaunchCfg> cand;
+            for (int rs : {0, 4, 8, 16})
+                for (int ds : {2, 4, 8})
+                    for (int so : {1, 0}) {
+                        if (!max_degree_dev && so == 0) continue;
+                        cand.push_back(LaunchCfg{rs, ds, so});
+                    }
+            double best = 1e300, first = 0.0;
+            LaunchCfg best_cfg = saved;
+            for (size_t c = 0; c < cand.size(); ++c) {
+                ctx->cfg = cand[c];
+                enqueue_eval(ctx, n_walk, R_dev, precision, max_degree_dev, sg.as<double>(),
+                             la.as<double>(), gl.as<double>(), ws.as<int32_t>(), st);
+                HIP_OK(hipEventRecord(e0, st));
+                for (int r = 0; r < n_rep; ++r)
+                    enqueue_eval(ctx, n_walk, R_dev, precision, max_degree_dev, sg.as<double>(),
+                                 la.as<double>(), gl.as<double>(), ws.as<int32_t>(), st);
+                HIP_OK(hipEventRecord(e1, st));
+                HIP_OK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+                const double per = ms / n_rep;
+                if (c == 0) first = per;
+                if (per < best) {
+                    best = per;
+                    best_cfg = cand[c];
+                }
+            }
+            ctx->cfg = best_cfg;
+            ctx->drop_graphs();
+            if (out) {
+                out->spmm_row_splits = best_cfg.spmm_rsplit;
+                out->direct_split = best_cfg.direct_split;
+                out->sort_walkers = best_cfg.sort_walkers;
+                out->n_candidates = (int32_t)cand.size();
+                out->best_ms = best;
+                out->default_ms = first;
+            }
+        } catch (...) {
+            ctx->cfg = saved;
+            cleanup();
+            throw;
+        }
+        cleanup();
     });
 }
 

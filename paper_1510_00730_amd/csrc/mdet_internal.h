@@ -49,6 +49,7 @@ struct SpinDev {
     int32_t e0;           // first electron index of this spin
     int32_t U;            // distinct determinants
     int32_t nchunk;       // adjugate chunks
+    int32_t deg_end[MDET_MAX_DEGREE + 1];  // execution-order end of degree <= d
     const int32_t *occ0;  // [n] reference occupied orbitals, ascending
     const DetDesc *desc;  // [U] in execution order (ascending degree)
     const int32_t *adj_off;    // [U+1] first adjugate slot of each determinant (sum of s^2)
@@ -75,6 +76,9 @@ struct SparseDev {
     const double *cval;    // [Z]
     const float *cval32;   // [Z]
     const int32_t *cseg64, *cseg32;  // [(nch+1)*V]
+    // end of the entries of row i (column j) whose column (row) determinant
+    // has degree <= d: rdeg[i*(MDET_MAX_DEGREE+1) + d]
+    const int32_t *rdeg, *cdeg;
 };
 
 // Per-call work buffers (device), sized for W walkers.
@@ -99,11 +103,24 @@ struct Work {
     double *psi64;     // [W][kPsiParts] partial sums of psi (FP64 in both precisions)
     int32_t *Rexp;     // [W][Upad+Vpad] direct-LU fallback: exponents of the determinants
     int32_t *Kmax;     // [W][2] direct-LU fallback: largest exponent (integer max)
-    double *dpart;     // [W][kDirectSplit][N][4] direct-LU fallback: derivative partial sums
+    double *dpart;     // [W][kDirectSplitMax][N][4] direct-LU fallback: derivative partial sums
+    // uneven batches: walkers sorted by maximum degree
+    int32_t *perm;     // [W] sorted position -> caller's walker
+    double *Rs;        // [W][N][3] positions in sorted order
+    int8_t *mds;       // [W] maximum degrees in sorted order
+    double *sign_s, *logabs_s, *gl_s;  // sorted-order outputs
+    int32_t *ws_s;
 };
 
-// Blocks per (walker, spin) of the direct-LU fallback.
-constexpr int kDirectSplit = 4;
+// Largest number of blocks per (walker, spin) of the direct-LU fallback.
+constexpr int kDirectSplitMax = 8;
+
+// Launch parameters chosen per context (mdet_autotune) or by default.
+struct LaunchCfg {
+    int32_t spmm_rsplit;   // row splits per 64-walker tile of the sparse product (0 = auto)
+    int32_t direct_split;  // blocks per (walker, spin) of the direct-LU fallback
+    int32_t sort_walkers;  // uneven batches: sort walkers by maximum degree
+};
 
 // Row splits of the sparse combination per walker tile (partial psi sums).
 constexpr int kPsiParts = 16;
@@ -120,6 +137,8 @@ struct KernelArgs {
     const int8_t *max_degree; // [W] or null
     int32_t precision;
     int32_t psi_nparts;       // row splits used by the sparse combination
+    int32_t direct_split;     // blocks per (walker, spin) of the direct-LU fallback
+    LaunchCfg cfg;
     double *sign_out, *logabs_out, *gl_out;
     int32_t *wstatus;
 };

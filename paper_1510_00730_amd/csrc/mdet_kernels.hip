@@ -640,11 +640,24 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
     const size_t RV = (size_t)a.wk.Upad + a.wk.Vpad;
     const size_t goff = pass ? 0 : (size_t)a.wk.Upad;   // gathered: R_up (pass 1) / R_dn (pass 0)
     const size_t ooff = pass ? (size_t)a.wk.Upad : 0;   // written: v / u
-    const int r0 = (int)((int64_t)nrows * rs / rsplit), r1 = (int)((int64_t)nrows * (rs + 1) / rsplit);
+    // uneven batches: the tile reaches only determinants (rows and columns in
+    // ascending-degree execution order) up to its walkers' largest degree
+    int dmax = MDET_MAX_DEGREE;
+    if (a.max_degree) {
+        int dm = active ? (int)a.max_degree[w] : 0;
+        for (int off = 32; off > 0; off >>= 1) dm = max(dm, __shfl_xor(dm, off, 64));
+        dmax = min(max(dm, 0), MDET_MAX_DEGREE);
+    }
+    const int32_t *__restrict__ degend = pass ? a.C.cdeg : a.C.rdeg;
+    const int nrows_eff = (pass ? a.sp[1] : a.sp[0]).deg_end[dmax];
+    const int ncols_eff = (pass ? a.sp[0] : a.sp[1]).deg_end[dmax];
+    const int r0 = (int)((int64_t)nrows * rs / rsplit);
+    const int r1 = min((int)((int64_t)nrows * (rs + 1) / rsplit), nrows_eff);
     double part = 0.0;
     for (int c = 0; c < nch; ++c) {
         const int cb = c * CC;
-        const int nc = min(CC, ncols - cb);
+        if (cb >= ncols_eff) break;
+        const int nc = min(CC, ncols_eff - cb);
         __syncthreads();
         // walker-major source: consecutive threads read consecutive entries of
         // one walker; the LDS row pitch kSpmmLd = 65 keeps both the stores here
@@ -655,7 +668,9 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
         }
         __syncthreads();
         for (int i = r0 + wave; i < r1; i += kSpmmWaves) {
-            const int kb = seg[(size_t)c * nrows + i], ke = seg[(size_t)(c + 1) * nrows + i];
+            const int kb = seg[(size_t)c * nrows + i];
+            const int ke = min(seg[(size_t)(c + 1) * nrows + i],
+                               degend[(size_t)i * (MDET_MAX_DEGREE + 1) + dmax]);
             const size_t o = (size_t)w * RV + ooff + i;
             F s = (c == 0 || !active) ? (F)0 : uv[o];
             // 8 nonzeros per step: their scalar loads and LDS reads are all in
@@ -683,10 +698,19 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                     }
                 }
             }
+            // tail: the same even/odd split by offset in the row, so that a
+            // shorter segment (entries skipped for an uneven batch, all zero)
+            // sums the remaining entries in exactly the same grouping
             for (; k < ke; ++k) {
                 const F x = val[k] * G[(idx[k] - cb) * kSpmmLd + lane];
-                if constexpr (COMP) two_sum_acc(s, comp, x);
-                else s += x;
+                const bool odd = ((k - kb) & 1) != 0;
+                if constexpr (COMP) {
+                    if (odd) two_sum_acc(s2, comp2, x);
+                    else two_sum_acc(s, comp, x);
+                } else {
+                    if (odd) s2 += x;
+                    else s += x;
+                }
             }
             if constexpr (COMP) {
                 two_sum_acc(s, comp, s2);
@@ -695,7 +719,8 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                 s += s2;
             }
             if (active) uv[o] = s;
-            if (pass == 0 && c == nch - 1 && active) part += (double)R[(size_t)w * RV + i] * (double)s;
+            if (pass == 0 && (c == nch - 1 || cb + CC >= ncols_eff) && active)
+                part += (double)R[(size_t)w * RV + i] * (double)s;
         }
     }
     if (pass == 0) {
@@ -803,7 +828,7 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
 // ---------------------------------------------------------------------------
 // Direct-LU fallback for an ill-conditioned reference: every determinant of
 // the (walker, spin) by its own LU, one thread per determinant with the
-// NT x NT matrix in registers (NT = electrons of the spin), kDirectSplit
+// NT x NT matrix in registers (NT = electrons of the spin), direct_split
 // blocks per (walker, spin).
 // ---------------------------------------------------------------------------
 namespace {
@@ -904,8 +929,8 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_ratios_t(KernelArgs a, 
     }
     __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
-    const int d0 = (int)((int64_t)S.U * part / kDirectSplit);
-    const int d1 = (int)((int64_t)S.U * (part + 1) / kDirectSplit);
+    const int d0 = (int)((int64_t)S.U * part / a.direct_split);
+    const int d1 = (int)((int64_t)S.U * (part + 1) / a.direct_split);
     int kmax = INT_MIN;
     for (int d = d0 + tid; d < d1; d += kDirectBlock) {
         const DetDesc D = S.desc[d];
@@ -957,8 +982,8 @@ __global__ void __launch_bounds__(kBlock) k_direct_scale(KernelArgs a) {
         a.wk.logdet0[ws] = 0.0;
         a.wk.sign0[ws] = 1.0;
     }
-    const int d0 = (int)((int64_t)S.U * part / kDirectSplit);
-    const int d1 = (int)((int64_t)S.U * (part + 1) / kDirectSplit);
+    const int d0 = (int)((int64_t)S.U * part / a.direct_split);
+    const int d1 = (int)((int64_t)S.U * (part + 1) / a.direct_split);
     for (int d = d0 + threadIdx.x; d < d1; d += kBlock) {
         const size_t o = rv_index(a, sp, d, w);
         const int e = a.wk.Rexp[o];
@@ -994,8 +1019,8 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a, i
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const int K = a.wk.K[ws];
     const bool mixed = a.precision == MDET_MIXED;
-    const int d0 = (int)((int64_t)S.U * part / kDirectSplit);
-    const int d1 = (int)((int64_t)S.U * (part + 1) / kDirectSplit);
+    const int d0 = (int)((int64_t)S.U * part / a.direct_split);
+    const int d1 = (int)((int64_t)S.U * (part + 1) / a.direct_split);
     double acc[NT][4];
 #pragma unroll
     for (int e = 0; e < NT; ++e)
@@ -1059,7 +1084,7 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a, i
     for (int i = tid; i < NT * 4; i += kDirectBlock) {
         double t = 0.0;
         for (int v = 0; v < kDirectBlock / 64; ++v) t += red[v * NT * 4 + i];
-        a.wk.dpart[(((size_t)w * kDirectSplit + part) * N + S.e0) * 4 + i] = t;
+        a.wk.dpart[(((size_t)w * kDirectSplitMax + part) * N + S.e0) * 4 + i] = t;
     }
 }
 
@@ -1085,8 +1110,8 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a) {
         const int e0 = a.sp[sp].e0, n = a.sp[sp].n;
         for (int t = 4 * e0; t < 4 * (e0 + n); ++t) {
             double s = 0.0;
-            for (int p = 0; p < kDirectSplit; ++p)
-                s += a.wk.dpart[((size_t)w * kDirectSplit + p) * a.N * 4 + t];
+            for (int p = 0; p < a.direct_split; ++p)
+                s += a.wk.dpart[((size_t)w * kDirectSplitMax + p) * a.N * 4 + t];
             a.gl_out[w * 4 * a.N + t] = s / psi;
         }
     }
@@ -1105,12 +1130,82 @@ const char *kernel_name(int k) {
     return (k >= 0 && k < kNumKernels) ? names[k] : "";
 }
 
+// ---------------------------------------------------------------------------
+// Uneven batches: stable counting sort of the walkers by maximum degree (one
+// block, deterministic), gather of positions and degrees, scatter of outputs.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) k_degree_sort(int64_t W, const int8_t *md, int32_t *perm) {
+    constexpr int D = MDET_MAX_DEGREE + 1;
+    __shared__ int cnt[1024][D];
+    __shared__ int base[D];
+    const int t = threadIdx.x;
+    const int64_t per = (W + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = min(W, b0 + per);
+    int c[D] = {0};
+    for (int64_t w = b0; w < b1; ++w) c[min(max((int)md[w], 0), D - 1)]++;
+    for (int d = 0; d < D; ++d) cnt[t][d] = c[d];
+    __syncthreads();
+    if (t < D) {  // exclusive scan over threads, per degree
+        int run = 0;
+        for (int k = 0; k < 1024; ++k) {
+            const int v = cnt[k][t];
+            cnt[k][t] = run;
+            run += v;
+        }
+        base[t] = run;
+    }
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int d = 0; d < D; ++d) {
+            const int v = base[d];
+            base[d] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    int pos[D];
+    for (int d = 0; d < D; ++d) pos[d] = base[d] + cnt[t][d];
+    for (int64_t w = b0; w < b1; ++w) {
+        const int d = min(max((int)md[w], 0), D - 1);
+        perm[pos[d]++] = (int32_t)w;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_sort_gather(int64_t W, int N, const int32_t *perm,
+                                                     const double *R, const int8_t *md, double *Rs,
+                                                     int8_t *mds) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= W * N * 3) return;
+    const int64_t k = t / (3 * N), r = t - k * 3 * N;
+    const int64_t w = perm[k];
+    Rs[t] = R[w * 3 * N + r];
+    if (r == 0) mds[k] = md[w];
+}
+
+__global__ void __launch_bounds__(256) k_sort_scatter(int64_t W, int N, const int32_t *perm,
+                                                      const double *sign_s, const double *logabs_s,
+                                                      const double *gl_s, const int32_t *ws_s,
+                                                      double *sign, double *logabs, double *gl,
+                                                      int32_t *ws) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= W * N * 4) return;
+    const int64_t k = t / (4 * N), r = t - k * 4 * N;
+    const int64_t w = perm[k];
+    gl[w * 4 * N + r] = gl_s[t];
+    if (r == 0) {
+        sign[w] = sign_s[k];
+        logabs[w] = logabs_s[k];
+        if (ws) ws[w] = ws_s[k];
+    }
+}
+
 namespace {
 
 template <int NT>
 void launch_direct(const KernelArgs &a, hipStream_t st, int sp, bool deriv) {
     const int M = a.M, W = (int)a.W;
-    const dim3 grid(W, kDirectSplit);
+    const dim3 grid(W, a.direct_split);
     if (deriv) {
         const size_t lds = sizeof(double) * (5 * (size_t)NT * M + (kDirectBlock / 64) * NT * 4) +
                            sizeof(int) * (M + NT);
@@ -1144,19 +1239,48 @@ void launch_direct_n(const KernelArgs &a, hipStream_t st, bool deriv) {
     }
 }
 
-int psi_splits(int64_t W) {
+int psi_splits(int64_t W, int requested) {
+    if (requested > 0) return std::max(1, std::min(requested, kPsiParts));
     const int64_t tiles = (W + kSpmmTile - 1) / kSpmmTile;
     const int rs = (int)((256 + tiles - 1) / tiles);
     return std::max(1, std::min(rs, kPsiParts));
 }
 
+hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev);
+
 }  // namespace
 
 hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
-    const int W = (int)args.W;
+    const int64_t W = args.W;
     if (W == 0) return hipSuccess;
     KernelArgs a = args;
-    a.psi_nparts = psi_splits(W);
+    a.psi_nparts = psi_splits(W, a.cfg.spmm_rsplit);
+    a.direct_split = std::max(1, std::min((int)a.cfg.direct_split, kDirectSplitMax));
+    if (!(a.max_degree && a.cfg.sort_walkers)) return launch_core(a, st, ev);
+    // uneven batch: evaluate the walkers in ascending order of maximum degree
+    const int N = a.N;
+    k_degree_sort<<<dim3(1), dim3(1024), 0, st>>>(W, a.max_degree, a.wk.perm);
+    k_sort_gather<<<dim3((unsigned)((W * N * 3 + 255) / 256)), dim3(256), 0, st>>>(
+        W, N, a.wk.perm, a.R, a.max_degree, a.wk.Rs, a.wk.mds);
+    KernelArgs b = a;
+    b.R = a.wk.Rs;
+    b.max_degree = a.wk.mds;
+    b.sign_out = a.wk.sign_s;
+    b.logabs_out = a.wk.logabs_s;
+    b.gl_out = a.wk.gl_s;
+    b.wstatus = a.wk.ws_s;
+    const hipError_t e = launch_core(b, st, ev);
+    if (e != hipSuccess) return e;
+    k_sort_scatter<<<dim3((unsigned)((W * N * 4 + 255) / 256)), dim3(256), 0, st>>>(
+        W, N, a.wk.perm, a.wk.sign_s, a.wk.logabs_s, a.wk.gl_s, a.wk.ws_s, a.sign_out, a.logabs_out,
+        a.gl_out, a.wstatus);
+    return hipGetLastError();
+}
+
+namespace {
+
+hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
+    const int W = (int)a.W;
     const int n = a.nmax, M = a.M;
     const dim3 g2(2 * W), blk(kBlock);
     auto mark = [&](int k) {
@@ -1170,7 +1294,7 @@ hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
     k_ratios<<<g2, blk, lds_rat, st>>>(a);
     mark(2);
     launch_direct_n(a, st, false);
-    k_direct_scale<<<dim3(2 * W, kDirectSplit), blk, 0, st>>>(a);
+    k_direct_scale<<<dim3(2 * W, a.direct_split), blk, 0, st>>>(a);
     mark(3);
     const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
     const dim3 gs(tiles * a.psi_nparts, 2), bs(64 * kSpmmWaves);
@@ -1193,5 +1317,7 @@ hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
     mark(7);
     return hipGetLastError();
 }
+
+}  // namespace
 
 }  // namespace mdet
