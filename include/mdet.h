@@ -283,12 +283,14 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
 /*
  * Launch parameters: spmm_row_splits = row splits per 64-walker tile of the
  * sparse combination (0 = derived from the batch, 1..16); direct_split =
- * blocks per (walker, spin) of the direct-LU fallback (1..8); sort_walkers =
+ * determinant slices (thread blocks) per flagged (walker, spin) of the
+ * direct-LU fallback (0 = one determinant per thread up to 8 slices, 1..8);
+ * sort_walkers =
  * with a max_degree array, evaluate the walkers in ascending order of their
  * maximum degree, so that each tile of the sparse combination touches only
  * the determinants its walkers reach.  FP64 results are bitwise reproducible
  * for a fixed configuration (the summation grouping depends on the splits).
- * Default (0, 4, 1).  Changing it drops captured graphs.
+ * Default (0, 0, 1).  Changing it drops captured graphs.
  */
 mdet_status mdet_set_launch_config(mdet_ctx *ctx, int32_t spmm_row_splits, int32_t direct_split,
                                    int32_t sort_walkers);
@@ -315,7 +317,7 @@ typedef struct {
 
 /*
  * Time every candidate launch configuration (row splits {auto, 4, 8, 16} x
- * fallback splits {2, 4, 8} x walker sorting {on, off} when max_degree_dev
+ * fallback splits {auto, 2, 4} x walker sorting {on, off} when max_degree_dev
  * is given) on n_rep evaluations of the given walkers, keep the fastest in
  * the context and report it in *out (nullable).  Synchronous.
  */

@@ -296,7 +296,7 @@ class Evaluator:
                                              self._stream(stream)))
 
     # -------------------------------------------------------------- tuning / graphs
-    def set_launch_config(self, spmm_row_splits=0, direct_split=4, sort_walkers=True):
+    def set_launch_config(self, spmm_row_splits=0, direct_split=0, sort_walkers=True):
         self._check(_LIB.mdet_set_launch_config(self._h, int(spmm_row_splits), int(direct_split),
                                                 1 if sort_walkers else 0))
 

@@ -92,10 +92,10 @@ struct mdet_ctx {
     std::vector<int32_t> row_i, col_j;
     std::vector<double> val;
     std::vector<int64_t> src_pos;
-    DevBuf d_rptr, d_rcol, d_rval, d_rval32, d_rseg, d_cptr, d_crow, d_cval, d_cval32, d_cseg;
+    DevBuf d_rptr, d_rcol, d_rval, d_rseg, d_cptr, d_crow, d_cval, d_cseg;
     DevBuf d_rseg32, d_cseg32, d_rdeg, d_cdeg;
     int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
-    LaunchCfg cfg{0, 4, 1};
+    LaunchCfg cfg{0, 0, 1};
     hipStream_t own_stream = nullptr;
     // captured evaluations (mdet_eval_graph), keyed by every argument
     struct GraphEntry {
@@ -152,8 +152,8 @@ struct mdet_ctx {
     }
     // walker work buffers
     int64_t wcap = 0;
-    DevBuf w_phi, w_E, w_X, w_T, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
-        w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart, w_perm, w_Rs, w_mds, w_sign_s, w_logabs_s, w_gl_s,
+    DevBuf w_phi, w_E, w_X, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
+        w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart, w_dcount, w_dlist, w_perm, w_Rs, w_mds, w_sign_s, w_logabs_s, w_gl_s,
         w_ws_s;
     Work wk{};
     // VMC / MLP work buffers (grow-only)
@@ -184,14 +184,14 @@ struct mdet_ctx {
             s = SpinHost();
         }
         drop_vmc();
-        for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_rseg, &d_cptr, &d_crow, &d_cval,
-                          &d_cval32, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
+        for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rseg, &d_cptr, &d_crow, &d_cval,
+                          &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             b->release();
         drop_work();
     }
     void drop_work() {
-        for (DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag, &w_K,
-                          &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp, &w_Kmax, &w_dpart,
+        for (DevBuf *b : {&w_phi, &w_E, &w_X, &w_g0, &w_logdet0, &w_sign0, &w_flag, &w_K,
+                          &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp, &w_Kmax, &w_dpart, &w_dcount, &w_dlist,
                           &w_perm, &w_Rs, &w_mds, &w_sign_s, &w_logabs_s, &w_gl_s, &w_ws_s})
             b->release();
         wcap = 0;
@@ -199,17 +199,17 @@ struct mdet_ctx {
     }
     int64_t work_bytes() const {
         int64_t t = 0;
-        for (const DevBuf *b : {&w_phi, &w_E, &w_X, &w_T, &w_g0, &w_logdet0, &w_sign0, &w_flag,
+        for (const DevBuf *b : {&w_phi, &w_E, &w_X, &w_g0, &w_logdet0, &w_sign0, &w_flag,
                                 &w_K, &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp,
-                                &w_Kmax, &w_dpart, &w_perm, &w_Rs, &w_mds, &w_sign_s,
+                                &w_Kmax, &w_dpart, &w_dcount, &w_dlist, &w_perm, &w_Rs, &w_mds, &w_sign_s,
                                 &w_logabs_s, &w_gl_s, &w_ws_s})
             t += (int64_t)b->bytes;
         return t;
     }
     int64_t exp_bytes() const {
         int64_t t = (int64_t)d_prim.bytes;
-        for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rval32, &d_rseg, &d_cptr, &d_crow,
-                                &d_cval, &d_cval32, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
+        for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rseg, &d_cptr, &d_crow,
+                                &d_cval, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             t += (int64_t)b->bytes;
         for (const auto &s : sp)
             t += (int64_t)(s.d_occ0.bytes + s.d_desc.bytes + s.d_adj_off.bytes +
@@ -437,7 +437,6 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     c->w_phi.alloc(sizeof(double) * W * N * 5 * M);
     c->w_E.alloc(sizeof(int32_t) * W * 2 * M);
     c->w_X.alloc(sizeof(double) * W * 2 * nmax * nmax);
-    c->w_T.alloc(sizeof(double) * W * 2 * nmax * M);
     c->w_g0.alloc(sizeof(double) * W * N * 4);
     c->w_logdet0.alloc(sizeof(double) * W * 2);
     c->w_sign0.alloc(sizeof(double) * W * 2);
@@ -451,6 +450,8 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     c->w_Rexp.alloc(sizeof(int32_t) * Wld * RV);
     c->w_Kmax.alloc(sizeof(int32_t) * W * 2);
     c->w_dpart.alloc(sizeof(double) * W * kDirectSplitMax * N * 4);
+    c->w_dcount.alloc(sizeof(int32_t));
+    c->w_dlist.alloc(sizeof(int32_t) * 2 * W);
     c->w_perm.alloc(sizeof(int32_t) * W);
     c->w_Rs.alloc(sizeof(double) * W * N * 3);
     c->w_mds.alloc(W);
@@ -469,7 +470,6 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     k.phi = c->w_phi.as<double>();
     k.E = c->w_E.as<int32_t>();
     k.X = c->w_X.as<double>();
-    k.T = c->w_T.as<double>();
     k.g0 = c->w_g0.as<double>();
     k.logdet0 = c->w_logdet0.as<double>();
     k.sign0 = c->w_sign0.as<double>();
@@ -483,6 +483,8 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     k.Rexp = c->w_Rexp.as<int32_t>();
     k.Kmax = c->w_Kmax.as<int32_t>();
     k.dpart = c->w_dpart.as<double>();
+    k.dcount = c->w_dcount.as<int32_t>();
+    k.dlist = c->w_dlist.as<int32_t>();
     k.perm = c->w_perm.as<int32_t>();
     k.Rs = c->w_Rs.as<double>();
     k.mds = c->w_mds.as<int8_t>();
@@ -533,11 +535,9 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.C.rptr = ctx->d_rptr.as<int32_t>();
     a.C.rcol = ctx->d_rcol.as<int32_t>();
     a.C.rval = ctx->d_rval.as<double>();
-    a.C.rval32 = ctx->d_rval32.as<float>();
     a.C.cptr = ctx->d_cptr.as<int32_t>();
     a.C.crow = ctx->d_crow.as<int32_t>();
     a.C.cval = ctx->d_cval.as<double>();
-    a.C.cval32 = ctx->d_cval32.as<float>();
     a.C.rseg64 = ctx->d_rseg.as<int32_t>();
     a.C.cseg64 = ctx->d_cseg.as<int32_t>();
     a.C.rseg32 = ctx->d_rseg32.as<int32_t>();
@@ -768,7 +768,6 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
                 cval[fc[je]++] = val[t];
             }
         }
-        std::vector<float> rval32(rval.begin(), rval.end()), cval32(cval.begin(), cval.end());
 
         // entries of each CSR row / CSC column whose other determinant has degree <= d
         constexpr int DD = MDET_MAX_DEGREE + 1;
@@ -807,11 +806,9 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->d_rptr.upload(rptr);
             ctx->d_rcol.upload(rcol);
             ctx->d_rval.upload(rval);
-            ctx->d_rval32.upload(rval32);
             ctx->d_cptr.upload(cptr);
             ctx->d_crow.upload(crow);
             ctx->d_cval.upload(cval);
-            ctx->d_cval32.upload(cval32);
             ctx->d_rseg.upload(rseg);
             ctx->d_cseg.upload(cseg);
             ctx->d_rseg32.upload(rseg32);
@@ -1130,8 +1127,8 @@ mdet_status mdet_set_launch_config(mdet_ctx *ctx, int32_t spmm_row_splits, int32
     return guarded(ctx, [&] {
         require(spmm_row_splits >= 0 && spmm_row_splits <= kPsiParts, MDET_EINVAL,
                 "spmm_row_splits must be 0 (auto) .. 16");
-        require(direct_split >= 1 && direct_split <= kDirectSplitMax, MDET_EINVAL,
-                "direct_split must be 1 .. 8");
+        require(direct_split >= 0 && direct_split <= kDirectSplitMax, MDET_EINVAL,
+                "direct_split must be 0 (auto) .. 8");
         ctx->cfg = LaunchCfg{spmm_row_splits, direct_split, sort_walkers ? 1 : 0};
         ctx->drop_graphs();
     });
@@ -1246,7 +1243,7 @@ mdet_status mdet_autotune(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, in
             HIP_OK(hipEventCreate(&e1));
             std::vector<LaunchCfg> cand;
             for (int rs : {0, 4, 8, 16})
-                for (int ds : {2, 4, 8})
+                for (int ds : {0, 2, 4})
                     for (int so : {1, 0}) {
                         if (!max_degree_dev && so == 0) continue;
                         cand.push_back(LaunchCfg{rs, ds, so});

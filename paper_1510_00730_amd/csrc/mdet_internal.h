@@ -69,12 +69,10 @@ struct SparseDev {
     const int32_t *rptr;   // [U+1] CSR (rows = up determinants)
     const int32_t *rcol;   // [Z]
     const double *rval;    // [Z]
-    const float *rval32;   // [Z]
     const int32_t *rseg64, *rseg32;  // [(nch+1)*U]
     const int32_t *cptr;   // [V+1] CSC (columns = down determinants)
     const int32_t *crow;   // [Z]
     const double *cval;    // [Z]
-    const float *cval32;   // [Z]
     const int32_t *cseg64, *cseg32;  // [(nch+1)*V]
     // end of the entries of row i (column j) whose column (row) determinant
     // has degree <= d: rdeg[i*(MDET_MAX_DEGREE+1) + d]
@@ -90,7 +88,6 @@ struct Work {
                        // sigma is used as phi * 2^-E[sigma][m])
     int32_t *E;        // [W][2][M] per-spin column exponents
     double *X;         // [W][2][nmax*nmax] inverse of the scaled reference
-    double *T;         // [W][2][nmax][M] table A^-1 Phi (scaled)
     double *g0;        // [W][N][4] grad~ D0 / D0
     double *logdet0;   // [W][2]
     double *sign0;     // [W][2]
@@ -104,6 +101,8 @@ struct Work {
     int32_t *Rexp;     // [W][Upad+Vpad] direct-LU fallback: exponents of the determinants
     int32_t *Kmax;     // [W][2] direct-LU fallback: largest exponent (integer max)
     double *dpart;     // [W][kDirectSplitMax][N][4] direct-LU fallback: derivative partial sums
+    int32_t *dcount;   // [1] direct-LU fallback: number of listed (walker, spin) pairs
+    int32_t *dlist;    // [2W] direct-LU fallback: listed pairs, w * 2 + spin (any order)
     // uneven batches: walkers sorted by maximum degree
     int32_t *perm;     // [W] sorted position -> caller's walker
     double *Rs;        // [W][N][3] positions in sorted order
@@ -118,7 +117,8 @@ constexpr int kDirectSplitMax = 8;
 // Launch parameters chosen per context (mdet_autotune) or by default.
 struct LaunchCfg {
     int32_t spmm_rsplit;   // row splits per 64-walker tile of the sparse product (0 = auto)
-    int32_t direct_split;  // blocks per (walker, spin) of the direct-LU fallback
+    int32_t direct_split;  // determinant slices per flagged (walker, spin) of the direct-LU
+                           // fallback (0 = one determinant per thread, at most kDirectSplitMax)
     int32_t sort_walkers;  // uneven batches: sort walkers by maximum degree
 };
 
@@ -137,7 +137,8 @@ struct KernelArgs {
     const int8_t *max_degree; // [W] or null
     int32_t precision;
     int32_t psi_nparts;       // row splits used by the sparse combination
-    int32_t direct_split;     // blocks per (walker, spin) of the direct-LU fallback
+    int32_t direct_split;     // determinant slices per listed pair of the direct-LU fallback
+    int32_t direct_stage_grad;  // fallback stages orbital derivatives in LDS (else reads HBM)
     LaunchCfg cfg;
     double *sign_out, *logabs_out, *gl_out;
     int32_t *wstatus;

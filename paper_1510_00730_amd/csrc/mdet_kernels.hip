@@ -35,39 +35,41 @@ constexpr int kMaxN = MDET_MAX_SPIN_ELEC;
 
 __device__ __forceinline__ double pow2(int k) { return ldexp(1.0, k); }
 
-// Axis factors of d^j/dx^j [x^a e^{-alpha x^2}] e^{+alpha x^2}, j = 0, 1, 2.
-__device__ __forceinline__ void axis3(double x, int a, double al, double &f0, double &f1,
-                                      double &f2) {
-    double p = 1.0, pm1 = 0.0, pm2 = 0.0;  // x^a, x^(a-1), x^(a-2) (0 when negative)
-    for (int i = 0; i < a; ++i) {
-        pm2 = pm1;
-        pm1 = p;
-        p *= x;
-    }
-    const double da = (double)a;
-    f0 = p;
-    f1 = da * pm1 - 2.0 * al * p * x;
-    f2 = da * (da - 1.0) * pm2 - 2.0 * al * (2.0 * da + 1.0) * p + 4.0 * al * al * p * x * x;
-}
+// Orbital m and its derivatives at one electron: value, grad x/y/z and
+// Laplacian of sum_p coef x^a y^b z^c exp(-alpha r^2).  Per axis, with
+// P_k = x^k:  d0 = P_a,  d1 = a P_(a-1) - 2 alpha P_(a+1),
+// d2 = a (a-1) P_(a-2) - 2 alpha (2a+1) P_a + 4 alpha^2 P_(a+2)
+// (the derivatives of x^a e^(-alpha x^2), divided by e^(-alpha x^2)).  The
+// powers come from a table: pw[axis * kPowLd + 2 + k] = P_k for k = 0..6 and 0
+// for k = -2, -1, so the terms with a negative power vanish without a branch
+// (no 0 * inf at a coordinate 0); r2 = |r|^2.
+constexpr int kPowLd = 9;
+constexpr size_t kPrimLdsMax = 32 * 1024;  // LDS for the primitives in the orbital kernel
 
-__device__ void orbital5(const Prim *prim, int P, int m, double x, double y, double z,
-                         double out[5]) {
-    const double r2 = x * x + y * y + z * z;
+__device__ __forceinline__ void orbital5_tab(const Prim *prim, int P, int m, const double *pw,
+                                             double r2, double out[5]) {
     double v = 0, gx = 0, gy = 0, gz = 0, lap = 0;
     for (int p = 0; p < P; ++p) {
         const Prim q = prim[m * P + p];
         if (q.coef == 0.0) continue;
         const double g = q.coef * exp(-q.alpha * r2);
-        double x0, x1, x2, y0, y1, y2, z0, z1, z2;
-        axis3(x, q.a, q.alpha, x0, x1, x2);
-        axis3(y, q.b, q.alpha, y0, y1, y2);
-        axis3(z, q.c, q.alpha, z0, z1, z2);
-        const double yz = y0 * z0;
-        v += g * x0 * yz;
-        gx += g * x1 * yz;
-        gy += g * x0 * y1 * z0;
-        gz += g * x0 * y0 * z1;
-        lap += g * (x2 * yz + x0 * (y2 * z0 + y0 * z2));
+        const double t2 = 2.0 * q.alpha, t4 = t2 * t2;
+        double f[3][3];
+        const int pa[3] = {q.a, q.b, q.c};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            const double *P0 = pw + ax * kPowLd + 2 + pa[ax];
+            const double da = (double)pa[ax];
+            f[ax][0] = P0[0];
+            f[ax][1] = da * P0[-1] - t2 * P0[1];
+            f[ax][2] = da * (da - 1.0) * P0[-2] - t2 * (2.0 * da + 1.0) * P0[0] + t4 * P0[2];
+        }
+        const double yz = f[1][0] * f[2][0];
+        v += g * f[0][0] * yz;
+        gx += g * f[0][1] * yz;
+        gy += g * f[0][0] * f[1][1] * f[2][0];
+        gz += g * f[0][0] * f[1][0] * f[2][1];
+        lap += g * (f[0][2] * yz + f[0][0] * (f[1][2] * f[2][0] + f[1][0] * f[2][2]));
     }
     out[0] = v;
     out[1] = gx;
@@ -83,28 +85,15 @@ __device__ __forceinline__ int expo(double x) {
     return k;
 }
 
-// deterministic block max / sum (blockDim.x == kBlock)
+// block max (blockDim.x == kBlock): wave maxima, then the kBlock / 64 of them
 __device__ int block_max_int(int v, int *red) {
-    red[threadIdx.x] = v;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + s]);
-        __syncthreads();
-    }
     int r = red[0];
-    __syncthreads();
-    return r;
-}
-
-template <typename F>
-__device__ F block_sum(F v, F *red) {
-    red[threadIdx.x] = v;
-    __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-        __syncthreads();
-    }
-    F r = red[0];
+#pragma unroll
+    for (int i = 1; i < kBlock / 64; ++i) r = max(r, red[i]);
     __syncthreads();
     return r;
 }
@@ -228,6 +217,14 @@ __device__ __forceinline__ bool gj_inverse(const double *m, double *inv, double 
     return true;
 }
 
+// a / b from the correctly rounded reciprocal rb = 1 / b and one FMA
+// correction (Markstein): correctly rounded away from overflow and underflow,
+// so equal rows still eliminate to exact zeros.
+__device__ __forceinline__ double div_by(double a, double b, double rb) {
+    const double q = a * rb;
+    return fma(fma(-q, b, a), rb, q);
+}
+
 // LU (partial pivoting) determinant of an S x S matrix, unrolled.
 template <int S>
 __device__ __forceinline__ double det_lu(const double *m) {
@@ -260,9 +257,10 @@ __device__ __forceinline__ double det_lu(const double *m) {
                 det = -det;
             }
         det *= a[j][j];
+        const double rinv = 1.0 / a[j][j];
 #pragma unroll
         for (int i = j + 1; i < S; ++i) {
-            const double l = a[i][j] / a[j][j];
+            const double l = div_by(a[i][j], a[j][j], rinv);
 #pragma unroll
             for (int k = j + 1; k < S; ++k) a[i][k] -= l * a[j][k];
         }
@@ -347,66 +345,85 @@ __device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// K1+K2+K3: orbitals, scaled reference inverse, refinement, table T, g0.
-// One block per (walker, spin).
+// K1+K2+K3: orbitals, scaled reference inverse, refinement, g0.
+// One block per walker.  The table T = X Phi' is not stored: the kernels
+// that use it rebuild it in LDS from X and the orbitals (build_table).
 // ---------------------------------------------------------------------------
 namespace {
 
-// Gauss-Jordan elimination with partial pivoting of the n x n matrix held one
-// row per lane (lanes 0..n-1 of one wave, n <= kMaxN): on return lane i
-// holds row i of the inverse in x[] and every lane the log|det| and sign.
-// Returns false on an exactly zero pivot.
-__device__ bool wave_gauss_jordan(int n, int lane, double (&r)[kMaxN], double (&x)[kMaxN],
-                                  double &logabs, double &sign) {
+// LDS hand-off between the lanes of one wave (no block barrier)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// In-place Gauss-Jordan inversion with partial pivoting of the n x n matrix
+// A (LDS, row-major, ld n) by the first 16 lanes of one wave, lane i holding
+// row i.  Rows are never exchanged: the pivot of column j is the unused lane
+// with the largest |entry| (lowest lane on ties), and the lane that pivots
+// column c ends up holding row c of A^-1 with column plane[j] in slot j.
+// The inverse is written to Xo (LDS, row-major); logabs and sign receive
+// ln|det A| and its sign.  Returns false on an exactly zero (or NaN) pivot.
+__device__ bool lane_gauss_jordan(int n, int lane, const double *A, double *Xo, double &logabs,
+                                  double &sign) {
+    double r[kMaxN];
 #pragma unroll
-    for (int k = 0; k < kMaxN; ++k) x[k] = (lane == k) ? 1.0 : 0.0;
+    for (int k = 0; k < kMaxN; ++k) r[k] = (lane < n && k < n) ? A[lane * n + k] : 0.0;
+    int pc = -1;
+    int plane[kMaxN];
     logabs = 0.0;
     sign = 1.0;
 #pragma unroll
     for (int j = 0; j < kMaxN; ++j) {
         if (j >= n) break;
-        double v = (lane >= j && lane < n) ? fabs(r[j]) : -1.0;
+        double v = (pc < 0 && lane < n) ? fabs(r[j]) : -1.0;
+        if (v != v) v = INFINITY;  // NaN: pick it, the result is flagged anyway
         int id = lane;
-        for (int off = 32; off > 0; off >>= 1) {
-            const double v2 = __shfl_xor(v, off, 64);
-            const int i2 = __shfl_xor(id, off, 64);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+            const double v2 = __shfl_xor(v, off, 16);
+            const int i2 = __shfl_xor(id, off, 16);
             if (v2 > v || (v2 == v && i2 < id)) {
                 v = v2;
                 id = i2;
             }
         }
-        if (!(v > 0.0)) return false;
-        const int src = (lane == j) ? id : ((lane == id) ? j : lane);
-        double pr[kMaxN], px[kMaxN];
-#pragma unroll
-        for (int k = 0; k < kMaxN; ++k) {
-            r[k] = __shfl(r[k], src, 64);
-            x[k] = __shfl(x[k], src, 64);
-        }
-#pragma unroll
-        for (int k = 0; k < kMaxN; ++k) {
-            pr[k] = __shfl(r[k], j, 64);
-            px[k] = __shfl(x[k], j, 64);
-        }
-        const double piv = pr[j];
-        if (id != j) sign = -sign;
-        if (piv < 0.0) sign = -sign;
-        logabs += log(fabs(piv));
+        id = __builtin_amdgcn_readfirstlane(id);
+        if (!(v > 0.0) || !(v < INFINITY)) return false;
+        plane[j] = id;
+        const double f = r[j];
+        const double piv = __shfl(f, id, 16);
         const double rinv = 1.0 / piv;
-        if (lane == j) {
+        logabs += log(fabs(piv));
+        if (piv < 0.0) sign = -sign;
+        if (lane == id) {
+            pc = j;
+            r[j] = 1.0;
 #pragma unroll
-            for (int k = 0; k < kMaxN; ++k) {
-                r[k] = pr[k] * rinv;
-                x[k] = px[k] * rinv;
-            }
-        } else {
-            const double f = r[j] * rinv;
-#pragma unroll
-            for (int k = 0; k < kMaxN; ++k) {
-                r[k] -= f * pr[k];
-                x[k] -= f * px[k];
-            }
+            for (int k = 0; k < kMaxN; ++k) r[k] *= rinv;
         }
+        double pr[kMaxN];
+#pragma unroll
+        for (int k = 0; k < kMaxN; ++k) pr[k] = (k < n) ? __shfl(r[k], id, 16) : 0.0;
+        if (lane != id) {
+            r[j] = 0.0;
+#pragma unroll
+            for (int k = 0; k < kMaxN; ++k) r[k] -= f * pr[k];
+        }
+    }
+    // det A = det(Q) prod piv, Q the permutation j -> plane[j]
+    int inv = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxN; ++i)
+#pragma unroll
+        for (int j = i + 1; j < kMaxN; ++j)
+            if (j < n && plane[i] > plane[j]) ++inv;
+    if (inv & 1) sign = -sign;
+    if (pc >= 0) {
+#pragma unroll
+        for (int j = 0; j < kMaxN; ++j)
+            if (j < n) Xo[pc * n + plane[j]] = r[j];
     }
     return true;
 }
@@ -414,138 +431,189 @@ __device__ bool wave_gauss_jordan(int n, int lane, double (&r)[kMaxN], double (&
 }  // namespace
 
 __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
-    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
-    const SpinDev S = a.sp[sp];
-    const int n = S.n, M = a.M, N = a.N, e0 = S.e0, tid = threadIdx.x;
+    const int w = blockIdx.x, tid = threadIdx.x;
+    const int M = a.M, N = a.N, nm = a.nmax, nn = nm * nm, nup = a.sp[0].n;
     extern __shared__ double lds[];
-    double *phi0 = lds;             // [n][M] scaled orbital values
-    double *scl = phi0 + n * M;     // [M]    2^-E[m]
-    double *Aor = scl + M;          // [n][n] scaled reference
-    double *Xs = Aor + n * n;       // [n][n]
-    double *Rm = Xs + n * n;        // [n][n]
-    int *Ex = (int *)(Rm + n * n);  // [M]
-    __shared__ int s_state;         // 0 ok, 2 singular
-    __shared__ double s_logabs, s_sign;
-    __shared__ double colA[kMaxN], colX[kMaxN];
-    const size_t ws = (size_t)w * 2 + sp;
+    double *Q = lds;                  // [2][5][nm*nm] orbitals (q = 0) and derivatives at the
+                                      // reference columns, Q[sp][q][e*n + c]
+    double *Xl = Q + 10 * nn;         // [2][nm*nm]
+    double *Rl = Xl + 2 * nn;         // [2][nm*nm]
+    int *emax = (int *)(Rl + 2 * nn); // [2][M] largest binary exponent of |phi| per column
+    int *slot = emax + 2 * M;         // [2][M] reference slot of orbital m, or -1
+    double *pw = (double *)(slot + 2 * M);  // [N][3][kPowLd] coordinate powers
+    double *r2s = pw + N * 3 * kPowLd;      // [N] |r|^2
+    // the primitives, staged when they fit (else read from HBM)
+    const bool stage_prim = (size_t)M * a.P * sizeof(Prim) <= kPrimLdsMax;
+    Prim *prl = (Prim *)(r2s + N);
+    const Prim *prim = stage_prim ? prl : a.prim;
+    if (stage_prim)
+        for (int i = tid; i < M * a.P; i += kBlock) prl[i] = a.prim[i];
 
-    double *phig = a.wk.phi + (size_t)w * N * 5 * M;
+    if (w == 0 && tid == 0) a.wk.dcount[0] = 0;  // fallback list, filled by k_ratios
+    for (int i = tid; i < 2 * M; i += kBlock) {
+        emax[i] = INT_MIN;
+        slot[i] = -1;
+    }
+    __syncthreads();
     const double *Rw = a.R + (size_t)w * N * 3;
-    // orbitals and derivatives, written once (unscaled)
-    for (int idx = tid; idx < n * M; idx += kBlock) {
-        const int e = idx / M, m = idx - e * M;
-        const double *r = Rw + 3 * (e0 + e);
-        double o[5];
-        orbital5(a.prim, a.P, m, r[0], r[1], r[2], o);
-        double *dst = phig + (size_t)(e0 + e) * 5 * M + m;
-        for (int q = 0; q < 5; ++q) dst[q * M] = o[q];
-        phi0[e * M + m] = o[0];
+    for (int i = tid; i < a.sp[0].n + a.sp[1].n; i += kBlock) {
+        const int sp = i >= nup, c = i - (sp ? nup : 0);
+        slot[sp * M + a.sp[sp].occ0[c]] = c;
     }
-    __syncthreads();
-    // power-of-two column scale of every orbital over this spin's electrons
-    for (int m = tid; m < M; m += kBlock) {
-        double mx = 0.0;
-        for (int e = 0; e < n; ++e) mx = fmax(mx, fabs(phi0[e * M + m]));
-        Ex[m] = expo(mx);
-        scl[m] = pow2(-Ex[m]);
-        a.wk.E[ws * M + m] = Ex[m];
-    }
-    __syncthreads();
-    for (int idx = tid; idx < n * M; idx += kBlock) phi0[idx] *= scl[idx % M];
-    __syncthreads();
-    for (int idx = tid; idx < n * n; idx += kBlock) {
-        const int e = idx / n, c = idx - e * n;
-        Aor[idx] = phi0[e * M + S.occ0[c]];
-    }
-    __syncthreads();
-    // inverse of the scaled reference by one wave (row per lane)
-    if (tid < 64) {
-        double r[kMaxN], x[kMaxN];
-#pragma unroll
-        for (int k = 0; k < kMaxN; ++k) r[k] = (tid < n && k < n) ? Aor[tid * n + k] : 0.0;
-        double la, sg;
-        const bool ok = wave_gauss_jordan(n, tid, r, x, la, sg);
-        if (ok && tid < n)
-            for (int k = 0; k < n; ++k) Xs[tid * n + k] = x[k];
-        if (tid == 0) {
-            s_state = ok ? 0 : 2;
-            s_logabs = la;
-            s_sign = sg;
+    for (int i = tid; i < N * 3; i += kBlock) {
+        const double x = Rw[i];
+        double *t = pw + i * kPowLd;
+        t[0] = 0.0;
+        t[1] = 0.0;
+        double p = 1.0;
+        for (int k = 0; k <= 6; ++k) {
+            t[2 + k] = p;
+            p *= x;
         }
     }
-    if (tid == 0) a.wk.Kmax[ws] = INT_MIN;
+    for (int e = tid; e < N; e += kBlock) {
+        const double *r = Rw + 3 * e;
+        r2s[e] = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+    }
     __syncthreads();
-    if (s_state) {
-        if (tid == 0) {
+    double *phig = a.wk.phi + (size_t)w * N * 5 * M;
+    // orbitals and derivatives, written once (unscaled)
+    for (int idx = tid; idx < N * M; idx += kBlock) {
+        const int e = idx / M, m = idx - e * M;
+        double o[5];
+        orbital5_tab(prim, a.P, m, pw + e * 3 * kPowLd, r2s[e], o);
+        double *dst = phig + (size_t)e * 5 * M + m;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) dst[q * M] = o[q];
+        const int sp = e >= nup, el = e - (sp ? nup : 0);
+        if (o[0] != 0.0) atomicMax(&emax[sp * M + m], expo(o[0]));
+        const int c = slot[sp * M + m];
+        if (c >= 0) {
+            const int n = a.sp[sp].n;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) Q[(sp * 5 + q) * nn + el * n + c] = o[q];
+        }
+    }
+    __syncthreads();
+    // power-of-two column scales E[sigma][m] (0 for an all-zero column)
+    for (int i = tid; i < 2 * M; i += kBlock) {
+        const int E = (emax[i] == INT_MIN) ? 0 : emax[i];
+        emax[i] = E;
+        a.wk.E[(size_t)w * 2 * M + i] = E;
+    }
+    __syncthreads();
+    for (int i = tid; i < 10 * nn; i += kBlock) {
+        const int sp = i / (5 * nn), r = i % nn;
+        const int n = a.sp[sp].n;
+        if (r < n * n) Q[i] *= pow2(-emax[sp * M + a.sp[sp].occ0[r % n]]);
+    }
+    __syncthreads();
+    // one wave per spin from here on
+    const int sp = tid >> 6, lane = tid & 63;
+    if (sp > 1) return;
+    const SpinDev S = a.sp[sp];
+    const int n = S.n;
+    const size_t ws = (size_t)w * 2 + sp;
+    const double *A = Q + sp * 5 * nn;
+    double *X = Xl + sp * nn, *Rm = Rl + sp * nn;
+    double la = 0.0, sg = 1.0;
+    bool ok = true;
+    if (lane < 16) ok = lane_gauss_jordan(n, lane, A, X, la, sg);
+    ok = __shfl(ok ? 1 : 0, 0, 64) != 0;
+    la = __shfl(la, 0, 64);
+    sg = __shfl(sg, 0, 64);
+    if (lane == 0) a.wk.Kmax[ws] = INT_MIN;
+    if (!ok) {
+        if (lane == 0) {
             a.wk.flag[ws] = 2;
             a.wk.logdet0[ws] = 0.0;
             a.wk.sign0[ws] = 1.0;
         }
         return;
     }
-    if (tid == 0) {
+    if (lane == 0) {
         int sx = 0;
-        for (int c = 0; c < n; ++c) sx += Ex[S.occ0[c]];
-        a.wk.logdet0[ws] = s_logabs + (double)sx * 0.69314718055994530942;
-        a.wk.sign0[ws] = s_sign;
+        for (int c = 0; c < n; ++c) sx += emax[sp * M + S.occ0[c]];
+        a.wk.logdet0[ws] = la + (double)sx * 0.69314718055994530942;
+        a.wk.sign0[ws] = sg;
     }
+    wave_lds_sync();
     // one residual-correction step: X <- X + X (I - A X)
-    for (int idx = tid; idx < n * n; idx += kBlock) {
+    for (int idx = lane; idx < n * n; idx += 64) {
         const int i = idx / n, j = idx - i * n;
         double t = (i == j) ? 1.0 : 0.0;
-        for (int k = 0; k < n; ++k) t -= Aor[i * n + k] * Xs[k * n + j];
+        for (int k = 0; k < n; ++k) t -= A[i * n + k] * X[k * n + j];
         Rm[idx] = t;
     }
-    __syncthreads();
-    double xr[4];
-    int nx = 0;
-    for (int idx = tid; idx < n * n; idx += kBlock) {
-        const int i = idx / n, j = idx - i * n;
-        double t = Xs[idx];
-        for (int k = 0; k < n; ++k) t += Xs[i * n + k] * Rm[k * n + j];
-        xr[nx++] = t;
+    wave_lds_sync();
+    double xr[kMaxN * kMaxN / 64];
+#pragma unroll
+    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
+        const int idx = lane + 64 * t;
+        if (idx < n * n) {
+            const int i = idx / n, j = idx - i * n;
+            double s = X[idx];
+            for (int k = 0; k < n; ++k) s += X[i * n + k] * Rm[k * n + j];
+            xr[t] = s;
+        }
     }
-    __syncthreads();
-    nx = 0;
-    for (int idx = tid; idx < n * n; idx += kBlock) Xs[idx] = xr[nx++];
-    __syncthreads();
-    const double *X = Xs;
-    if (tid < n) {
-        double ca = 0.0, cx = 0.0;
+    wave_lds_sync();
+    double *Xg = a.wk.X + ws * nn;
+#pragma unroll
+    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
+        const int idx = lane + 64 * t;
+        if (idx < n * n) {
+            X[idx] = xr[t];
+            Xg[idx] = xr[t];
+        }
+    }
+    wave_lds_sync();
+    // conditioning: kappa_1 = ||A||_1 ||X||_1 (largest column sums)
+    double ca = 0.0, cx = 0.0;
+    if (lane < n)
         for (int i = 0; i < n; ++i) {
-            ca += fabs(Aor[i * n + tid]);
-            cx += fabs(X[i * n + tid]);
+            ca += fabs(A[i * n + lane]);
+            cx += fabs(X[i * n + lane]);
         }
-        colA[tid] = ca;
-        colX[tid] = cx;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ca = fmax(ca, __shfl_xor(ca, off, 64));
+        cx = fmax(cx, __shfl_xor(cx, off, 64));
     }
-    __syncthreads();
-    if (tid == 0) {
-        double na = 0.0, nxm = 0.0;
-        for (int c = 0; c < n; ++c) {
-            na = fmax(na, colA[c]);
-            nxm = fmax(nxm, colX[c]);
-        }
-        const double kappa = na * nxm;
-        a.wk.flag[ws] = (kappa <= a.kappa_max) ? 0 : 1;  // NaN -> fallback
-    }
-    double *Xg = a.wk.X + ws * a.nmax * a.nmax;
-    for (int idx = tid; idx < n * n; idx += kBlock) Xg[idx] = X[idx];
-    double *Tg = a.wk.T + ws * a.nmax * M;
-    for (int idx = tid; idx < n * M; idx += kBlock) {
-        const int c = idx / M, m = idx - c * M;
+    if (lane == 0) a.wk.flag[ws] = (ca * cx <= a.kappa_max) ? 0 : 1;  // NaN -> fallback
+    // grad~_e D0 / D0 = sum_c X[c][e] grad~ Phi'[e][occ0[c]]
+    if (lane < 4 * n) {
+        const int e = lane >> 2, q = lane & 3;
+        const double *G = Q + (sp * 5 + 1 + q) * nn;
         double t = 0.0;
-        for (int e = 0; e < n; ++e) t += X[c * n + e] * phi0[e * M + m];
-        Tg[idx] = t;
-    }
-    for (int idx = tid; idx < 4 * n; idx += kBlock) {
-        const int e = idx >> 2, q = idx & 3;
-        const double *g = phig + (size_t)(e0 + e) * 5 * M + (size_t)(1 + q) * M;
-        double t = 0.0;
-        for (int c = 0; c < n; ++c) t += X[c * n + e] * (g[S.occ0[c]] * scl[S.occ0[c]]);
-        a.wk.g0[((size_t)w * N + e0 + e) * 4 + q] = t;
+        for (int c = 0; c < n; ++c) t += X[c * n + e] * G[e * n + c];
+        a.wk.g0[((size_t)w * N + S.e0 + e) * 4 + q] = t;
     }
 }
+
+namespace {
+
+// T = X Phi' of one (walker, spin) into LDS: T[c][m] = sum_e X[c][e] phi[e][m] 2^-E[m]
+// (X in LDS, row-major n x n; phis = values of the spin's first electron, row
+// stride 5 M).  One column m per thread, e ascending.
+__device__ __forceinline__ void build_table(const double *phis, int n, int M, const int *Ex,
+                                            const double *X, double *T, int tid, int nthr) {
+    for (int m = tid; m < M; m += nthr) {
+        const double s = pow2(-Ex[m]);
+        double col[kMaxN];
+#pragma unroll
+        for (int e = 0; e < kMaxN; ++e) col[e] = (e < n) ? phis[(size_t)e * 5 * M + m] * s : 0.0;
+        for (int c = 0; c < n; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int e = 0; e < kMaxN; ++e)
+                if (e < n) t += X[c * n + e] * col[e];
+            T[c * M + m] = t;
+        }
+    }
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // K4: ratios R_d / 2^K of every distinct determinant (table method).
@@ -554,22 +622,50 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
 __global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
     const size_t ws = (size_t)w * 2 + sp;
-    if (a.wk.flag[ws] != 0) return;
+    if (a.wk.flag[ws] != 0) {  // ill-conditioned: queue the pair for the direct-LU fallback
+        if (threadIdx.x == 0) a.wk.dlist[atomicAdd(a.wk.dcount, 1)] = (int32_t)ws;
+        return;
+    }
     const SpinDev S = a.sp[sp];
     const int n = S.n, M = a.M, tid = threadIdx.x;
     extern __shared__ double lds[];
     double *T = lds;                 // [n][M]
-    int *Ex = (int *)(T + n * M);    // [M]
+    double *X = T + n * M;           // [n][n]
+    int *Ex = (int *)(X + n * n);    // [M]
     int *occ0 = Ex + M;              // [n]
     __shared__ int red[kBlock];
-    const double *Tg = a.wk.T + ws * a.nmax * M;
-    for (int idx = tid; idx < n * M; idx += kBlock) T[idx] = Tg[idx];
+    const double *Xg = a.wk.X + ws * a.nmax * a.nmax;
+    for (int i = tid; i < n * n; i += kBlock) X[i] = Xg[i];
     for (int m = tid; m < M; m += kBlock) Ex[m] = a.wk.E[ws * M + m];
     for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
     __syncthreads();
+    build_table(a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M, n, M, Ex, X, T, tid, kBlock);
+    __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
+    const bool mixed = a.precision == MDET_MIXED;
+    // the first kKeep determinants of every thread stay in registers until the
+    // shift K is known; further ones go through the ratio vector in HBM
+    constexpr int kKeep = 4;
+    double rk[kKeep];
+    int xk[kKeep];
     int kmax = INT_MIN;
-    for (int d = tid; d < S.U; d += kBlock) {
+#pragma unroll
+    for (int j = 0; j < kKeep; ++j) {
+        const int d = tid + j * kBlock;
+        double r = 0.0;
+        int dx = 0;
+        if (d < S.U) {
+            const DetDesc D = S.desc[d];
+            if (D.s <= dmax) {
+                r = ratio_any(D, T, M);
+                dx = delta_exponent(D, Ex, occ0);
+                if (r != 0.0) kmax = max(kmax, expo(r) + dx);
+            }
+        }
+        rk[j] = r;
+        xk[j] = dx;
+    }
+    for (int d = tid + kKeep * kBlock; d < S.U; d += kBlock) {
         const DetDesc D = S.desc[d];
         double r = 0.0;
         if (D.s <= dmax) {
@@ -581,11 +677,21 @@ __global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
     int K = block_max_int(kmax, red);
     if (K == INT_MIN) K = 0;
     if (tid == 0) a.wk.K[ws] = K;
-    for (int d = tid; d < S.U; d += kBlock) {
+#pragma unroll
+    for (int j = 0; j < kKeep; ++j) {
+        const int d = tid + j * kBlock;
+        if (d < S.U) {
+            const size_t o = rv_index(a, sp, d, w);
+            const double r = ldexp(rk[j], xk[j] - K);
+            if (mixed) a.wk.R32[o] = (float)r;
+            else a.wk.R64[o] = r;
+        }
+    }
+    for (int d = tid + kKeep * kBlock; d < S.U; d += kBlock) {
         const DetDesc D = S.desc[d];
         const size_t o = rv_index(a, sp, d, w);
         const double r = ldexp(a.wk.R64[o], delta_exponent(D, Ex, occ0) - K);
-        if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
+        if (mixed) a.wk.R32[o] = (float)r;
         else a.wk.R64[o] = r;
     }
 }
@@ -596,47 +702,59 @@ __global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
 //   pass 0:  u = C R_dn  (CSR rows, gathering R_dn)  and the psi partials R_up . u
 //   pass 1:  v = C^T R_up (CSC columns, gathering R_up)
 // A wave owns whole rows, so the entries of C are wave-uniform (scalar loads)
-// and each one feeds 64 fused multiply-adds; the gathered vector of the 64
-// walkers sits in LDS, CC entries at a time.  The kernel is bound by LDS
-// bandwidth, which leaves ALU slack: the FP32 variant spends it on a
-// compensated (TwoSum) accumulation.  grid.x = walker tiles x row splits,
-// grid.y = pass.
+// and each one feeds 64 multiply-adds; the gathered vector of the 64 walkers
+// sits in LDS, CC entries at a time.  F is the storage type of R, u and v
+// (float in mixed precision: half the bytes and twice the columns per LDS
+// chunk); C and the accumulation are FP64 in both precisions (a product of a
+// float and a double converted from float is exact in FP64).
+// grid.x = walker tiles x row splits, grid.y = pass.
 // ---------------------------------------------------------------------------
 constexpr int kSpmmWaves = 16;
 constexpr int kSpmmLd = kSpmmTile + 1;  // LDS row pitch of the staged vector
+constexpr int kSpmmGroup = 8;           // nonzeros per step of the inner loop
 
-// s + x with the rounding error of the addition carried in comp (TwoSum)
-template <typename F>
-__device__ __forceinline__ void two_sum_acc(F &s, F &comp, F x) {
-#pragma clang fp contract(off)
-    const F t = s + x;
-    const F z = t - s;
-    comp += (s - (t - z)) + (x - z);
-    s = t;
+// LDS hand-off between the lanes of one wave (no block barrier)
+__device__ __forceinline__ void spmm_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename F, int CC, bool COMP>
+// Block -> (walker tile, row split): blocks are dealt to the 8 XCDs round
+// robin, so the row splits of one tile are kept on one XCD (its L2 then holds
+// the tile's gathered vector for all of them).  gridDim.x = ceil(tiles / 8) *
+// 8 * rsplit; blocks past the last tile do nothing.
+__device__ __forceinline__ void spmm_block_map(int b, int rsplit, int &tile, int &rs) {
+    const int x = b & 7, y = b >> 3;
+    tile = x + 8 * (y / rsplit);
+    rs = y - (y / rsplit) * rsplit;
+}
+
+template <typename F, int CC>
 __global__ void __launch_bounds__(64 * kSpmmWaves)
     k_spmm(KernelArgs a, const F *__restrict__ R, F *__restrict__ uv,
-           const F *__restrict__ rval, const F *__restrict__ cval,
+           const double *__restrict__ rval, const double *__restrict__ cval,
            const int32_t *__restrict__ rcol, const int32_t *__restrict__ crow,
            const int32_t *__restrict__ rseg, const int32_t *__restrict__ cseg, int nch_r, int nch_c,
            int rsplit) {
     __shared__ F G[CC * kSpmmLd];
     __shared__ double red[kSpmmWaves][kSpmmTile];
+    __shared__ int Cj[kSpmmWaves][64];     // per wave: LDS offsets of a row's next 64 nonzeros
+    __shared__ double Cv[kSpmmWaves][64];  // and their values
     const int pass = blockIdx.y;
-    const int tile = blockIdx.x / rsplit, rs = blockIdx.x - tile * rsplit;
+    int tile, rs;
+    spmm_block_map(blockIdx.x, rsplit, tile, rs);
     const int W = (int)a.W;
+    if (tile * kSpmmTile >= W) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int w0 = tile * kSpmmTile, w = w0 + lane;
     const bool active = w < W;
     const int nrows = pass ? a.C.V : a.C.U;
-    const int ncols = pass ? a.C.U : a.C.V;
     const int nch = pass ? nch_c : nch_r;
     const int32_t *__restrict__ idx = pass ? crow : rcol;
     const int32_t *__restrict__ seg = pass ? cseg : rseg;
-    const F *__restrict__ val = pass ? cval : rval;
+    const double *__restrict__ val = pass ? cval : rval;
     const size_t RV = (size_t)a.wk.Upad + a.wk.Vpad;
     const size_t goff = pass ? 0 : (size_t)a.wk.Upad;   // gathered: R_up (pass 1) / R_dn (pass 0)
     const size_t ooff = pass ? (size_t)a.wk.Upad : 0;   // written: v / u
@@ -653,74 +771,102 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
     const int ncols_eff = (pass ? a.sp[0] : a.sp[1]).deg_end[dmax];
     const int r0 = (int)((int64_t)nrows * rs / rsplit);
     const int r1 = min((int)((int64_t)nrows * (rs + 1) / rsplit), nrows_eff);
+    int *cj = Cj[wave];
+    double *cv = Cv[wave];
     double part = 0.0;
     for (int c = 0; c < nch; ++c) {
         const int cb = c * CC;
         if (cb >= ncols_eff) break;
         const int nc = min(CC, ncols_eff - cb);
         __syncthreads();
-        // walker-major source: consecutive threads read consecutive entries of
-        // one walker; the LDS row pitch kSpmmLd = 65 keeps both the stores here
-        // and the lane-contiguous reads below free of bank conflicts
-        for (int t = threadIdx.x; t < nc * kSpmmTile; t += 64 * kSpmmWaves) {
-            const int ww = t / nc, jj = t - ww * nc;
-            G[jj * kSpmmLd + ww] = (w0 + ww < W) ? R[(size_t)(w0 + ww) * RV + goff + cb + jj] : (F)0;
+        // stage G[j][walker]: each wave copies kSpmmTile / kSpmmWaves whole
+        // walker rows (walker-major source, coalesced), all loads in flight
+        // before the stores; the odd LDS pitch keeps the stores here and the
+        // lane-contiguous reads below free of bank conflicts
+        {
+            constexpr int kRows = kSpmmTile / kSpmmWaves;
+            constexpr int kIt = (CC + 63) / 64;
+            F buf[kRows][kIt];
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                const int ww = wave + kSpmmWaves * r;
+                const F *src = R + (size_t)(w0 + ww) * RV + goff + cb;
+                const bool ok = w0 + ww < W;
+#pragma unroll
+                for (int q = 0; q < kIt; ++q) {
+                    const int jj = lane + 64 * q;
+                    buf[r][q] = (F)0;
+                    if (ok && jj < nc) buf[r][q] = src[jj];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kRows; ++r)
+#pragma unroll
+                for (int q = 0; q < kIt; ++q) {
+                    const int jj = lane + 64 * q;
+                    if (jj < nc) G[jj * kSpmmLd + wave + kSpmmWaves * r] = buf[r][q];
+                }
         }
         __syncthreads();
-        for (int i = r0 + wave; i < r1; i += kSpmmWaves) {
-            const int kb = seg[(size_t)c * nrows + i];
-            const int ke = min(seg[(size_t)(c + 1) * nrows + i],
-                               degend[(size_t)i * (MDET_MAX_DEGREE + 1) + dmax]);
-            const size_t o = (size_t)w * RV + ooff + i;
-            F s = (c == 0 || !active) ? (F)0 : uv[o];
-            // 8 nonzeros per step: their scalar loads and LDS reads are all in
-            // flight before the first multiply-add; two independent sums
-            F s2 = 0, comp = 0, comp2 = 0;
-            int k = kb;
-            for (; k + 8 <= ke; k += 8) {
-                int jx[8];
-                F vx[8], gx[8];
-#pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    jx[t] = idx[k + t];
-                    vx[t] = val[k + t];
-                }
-#pragma unroll
-                for (int t = 0; t < 8; ++t) gx[t] = G[(jx[t] - cb) * kSpmmLd + lane];
-#pragma unroll
-                for (int t = 0; t < 8; t += 2) {
-                    if constexpr (COMP) {
-                        two_sum_acc(s, comp, vx[t] * gx[t]);
-                        two_sum_acc(s2, comp2, vx[t + 1] * gx[t + 1]);
-                    } else {
-                        s += vx[t] * gx[t];
-                        s2 += vx[t + 1] * gx[t + 1];
+        // the wave's rows i = r0 + wave + kSpmmWaves * j, row bounds for up to
+        // 64 rows at a time held one per lane
+        for (int rb = r0 + wave; rb < r1; rb += kSpmmWaves * 64) {
+            const int ir = rb + kSpmmWaves * lane;
+            int kbv = 0, kev = 0;
+            if (ir < r1) {
+                kbv = seg[(size_t)c * nrows + ir];
+                kev = min(seg[(size_t)(c + 1) * nrows + ir],
+                          degend[(size_t)ir * (MDET_MAX_DEGREE + 1) + dmax]);
+            }
+            const int nr = min(64, (r1 - rb + kSpmmWaves - 1) / kSpmmWaves);
+            for (int jr = 0; jr < nr; ++jr) {
+                const int i = rb + kSpmmWaves * jr;
+                const int kb = __builtin_amdgcn_readlane(kbv, jr);
+                const int ke = __builtin_amdgcn_readlane(kev, jr);
+                const size_t o = (size_t)w * RV + ooff + i;
+                // two independent sums: even / odd offsets in the row segment
+                double s = 0.0, s2 = 0.0;
+                if (c != 0 && active) s = (double)uv[o];
+                for (int base = kb; base < ke; base += 64) {
+                    const int cnt = min(64, ke - base);
+                    int jl = 0;
+                    double vl = 0.0;
+                    if (lane < cnt) {
+                        jl = (idx[base + lane] - cb) * kSpmmLd;
+                        vl = val[base + lane];
                     }
+                    cj[lane] = jl;
+                    cv[lane] = vl;
+                    spmm_wave_sync();
+                    int t = 0;
+                    for (; t + kSpmmGroup <= cnt; t += kSpmmGroup) {
+                        F gx[kSpmmGroup];
+#pragma unroll
+                        for (int u = 0; u < kSpmmGroup; ++u) gx[u] = G[cj[t + u] + lane];
+#pragma unroll
+                        for (int u = 0; u < kSpmmGroup; u += 2) {
+                            s = fma(cv[t + u], (double)gx[u], s);
+                            s2 = fma(cv[t + u + 1], (double)gx[u + 1], s2);
+                        }
+                    }
+                    // tail: the same even/odd split by offset in the row, so
+                    // that a shorter segment (entries skipped for an uneven
+                    // batch, all zero) sums in exactly the same grouping
+                    for (; t < cnt; ++t) {
+                        const double x = (double)G[cj[t] + lane];
+                        if ((base - kb + t) & 1) s2 = fma(cv[t], x, s2);
+                        else s = fma(cv[t], x, s);
+                    }
+                    spmm_wave_sync();
                 }
+                // u and v are rounded to F here after every chunk; psi takes
+                // the stored value, so it does not depend on how many chunks
+                // the tile needed (walker order in an uneven batch)
+                const F sf = (F)(s + s2);
+                if (active) uv[o] = sf;
+                if (pass == 0 && (c == nch - 1 || cb + CC >= ncols_eff) && active)
+                    part += (double)R[(size_t)w * RV + i] * (double)sf;
             }
-            // tail: the same even/odd split by offset in the row, so that a
-            // shorter segment (entries skipped for an uneven batch, all zero)
-            // sums the remaining entries in exactly the same grouping
-            for (; k < ke; ++k) {
-                const F x = val[k] * G[(idx[k] - cb) * kSpmmLd + lane];
-                const bool odd = ((k - kb) & 1) != 0;
-                if constexpr (COMP) {
-                    if (odd) two_sum_acc(s2, comp2, x);
-                    else two_sum_acc(s, comp, x);
-                } else {
-                    if (odd) s2 += x;
-                    else s += x;
-                }
-            }
-            if constexpr (COMP) {
-                two_sum_acc(s, comp, s2);
-                s += comp + comp2;
-            } else {
-                s += s2;
-            }
-            if (active) uv[o] = s;
-            if (pass == 0 && (c == nch - 1 || cb + CC >= ncols_eff) && active)
-                part += (double)R[(size_t)w * RV + i] * (double)s;
         }
     }
     if (pass == 0) {
@@ -742,7 +888,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
 __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
     const size_t ws = (size_t)w * 2 + sp;
-    if (a.wk.flag[ws] != 0) return;
+    if (a.wk.flag[ws] != 0 || a.sp[sp].n == 0) return;
     const SpinDev S = a.sp[sp];
     const int n = S.n, M = a.M, N = a.N, tid = threadIdx.x;
     const int nt = n * M;
@@ -752,18 +898,18 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     double *Gam = X + n * n;          // [n][M]  Gamma[c][m]
     double *Y = Gam + nt;             // [M][n]
     double *Zc = Y + nt;              // [n][n]
-    double *cb = Zc + n * n;          // [kAdjChunk]
+    double *cb = Zc + n * n;          // [kAdjChunk] staged adjugates (later: partial sums)
     int *Ex = (int *)(cb + kAdjChunk); // [M]
     int *occ0 = Ex + M;               // [n]
-    const double *Tg = a.wk.T + ws * a.nmax * M;
-    for (int i = tid; i < nt; i += kBlock) {
-        T[i] = Tg[i];
-        Gam[i] = 0.0;
-    }
+    int *gpl = occ0 + n;              // [n*M + 1] the chunk's gather pointers
+    uint16_t *gpo = (uint16_t *)(gpl + nt + 1);  // [kAdjChunk] the chunk's gather positions
+    for (int i = tid; i < nt; i += kBlock) Gam[i] = 0.0;
     const double *Xg = a.wk.X + ws * a.nmax * a.nmax;
     for (int i = tid; i < n * n; i += kBlock) X[i] = Xg[i];
     for (int m = tid; m < M; m += kBlock) Ex[m] = a.wk.E[ws * M + m];
     for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
+    __syncthreads();
+    build_table(a.wk.phi + ((size_t)w * N + S.e0) * 5 * M, n, M, Ex, X, T, tid, kBlock);
     __syncthreads();
     const int K = a.wk.K[ws];
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
@@ -771,6 +917,11 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     for (int k = 0; k < S.nchunk; ++k) {
         const int d0 = S.chunk_det[k], d1 = S.chunk_det[k + 1];
         const int base = S.adj_off[d0];
+        // the chunk's gather lists, copied to LDS while the adjugates are staged
+        const int32_t *gp = S.gptr + (size_t)k * (nt + 1);
+        const int q0 = gp[0], nq = S.adj_off[d1] - base;
+        for (int t = tid; t <= nt; t += kBlock) gpl[t] = gp[t] - q0;
+        for (int q = tid; q < nq; q += kBlock) gpo[q] = S.gpos[q0 + q];
         for (int d = d0 + tid; d < d1; d += kBlock) {
             const DetDesc D = S.desc[d];
             const int s = D.s;
@@ -790,10 +941,9 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
             }
         }
         __syncthreads();
-        const int32_t *gp = S.gptr + (size_t)k * (nt + 1);
         for (int t = tid; t < nt; t += kBlock) {
             double g = 0.0;
-            for (int q = gp[t]; q < gp[t + 1]; ++q) g += cb[S.gpos[q]];
+            for (int q = gpl[t]; q < gpl[t + 1]; ++q) g += cb[gpo[q]];
             Gam[t] += g;
         }
         __syncthreads();
@@ -805,51 +955,79 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
         Y[idx] = s;
     }
     __syncthreads();
-    for (int idx = tid; idx < n * n; idx += kBlock) {
+    // Zc = T Y: nz segments of m per entry, partial sums in cb
+    const int nz = max(1, min(4, kBlock / (n * n)));
+    if (tid < nz * n * n) {
+        const int idx = tid / nz, g = tid - idx * nz;
         const int c = idx / n, e = idx - c * n;
         double s = 0.0;
-        for (int m = 0; m < M; ++m) s += T[c * M + m] * Y[m * n + e];
+        for (int m = g; m < M; m += nz) s += T[c * M + m] * Y[m * n + e];
+        cb[tid] = s;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < n * n; idx += kBlock) {
+        double s = 0.0;
+        for (int g = 0; g < nz; ++g) s += cb[idx * nz + g];
         Zc[idx] = s;
     }
     __syncthreads();
-    const double psi = psi_value(a, w);
-    const double *phig = a.wk.phi + (size_t)w * N * 5 * M;
-    for (int idx = tid; idx < 4 * n; idx += kBlock) {
-        const int e = idx >> 2, q = idx & 3;
-        const double *Gq = phig + (size_t)(S.e0 + e) * 5 * M + (size_t)(1 + q) * M;
+    // s1[e][q] = sum_m G_q[e][m] 2^-E[m] Y[m][e]: kFin segments of m per (e, q)
+    constexpr int kFin = 4;
+    const double *phig = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
+    if (tid < kFin * 4 * n) {
+        const int pr = tid / kFin, g = tid - pr * kFin;
+        const int e = pr >> 2, q = pr & 3;
+        const double *Gq = phig + (size_t)e * 5 * M + (size_t)(1 + q) * M;
+        double s = 0.0;
+        for (int m = g; m < M; m += kFin) s += (Gq[m] * pow2(-Ex[m])) * Y[m * n + e];
+        cb[tid] = s;
+    }
+    __syncthreads();
+    if (tid < 4 * n) {
+        const int e = tid >> 2, q = tid & 3;
+        const double *Gq = phig + (size_t)e * 5 * M + (size_t)(1 + q) * M;
         double s1 = 0.0, s2 = 0.0;
-        for (int m = 0; m < M; ++m) s1 += (Gq[m] * pow2(-Ex[m])) * Y[m * n + e];
+        for (int g = 0; g < kFin; ++g) s1 += cb[tid * kFin + g];
         for (int c = 0; c < n; ++c) s2 += (Gq[occ0[c]] * pow2(-Ex[occ0[c]])) * Zc[c * n + e];
         const size_t o = ((size_t)w * N + S.e0 + e) * 4 + q;
-        a.gl_out[o] = a.wk.g0[o] + (s1 - s2) / psi;
+        a.gl_out[o] = a.wk.g0[o] + (s1 - s2) / psi_value(a, w);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Direct-LU fallback for an ill-conditioned reference: every determinant of
-// the (walker, spin) by its own LU, one thread per determinant with the
-// NT x NT matrix in registers (NT = electrons of the spin), direct_split
-// blocks per (walker, spin).
+// Direct-LU fallback for an ill-conditioned reference: every determinant of a
+// flagged (walker, spin) by its own LU with partial pivoting, one thread per
+// determinant with the matrix in registers (the analogue of the O(n^3)
+// recomputation rule for failed updates, Sec. 2.2).  k_ratios lists the
+// flagged pairs; a work item is (pair, part), part = one of direct_split
+// slices of the pair's determinants, and a fixed grid walks the items.  One
+// launch serves both spins: K x K matrices are compiled for K = NT and NT-1
+// (NT = the larger electron count); a smaller spin is padded with an
+// identity block, which changes neither its determinant nor its inverse.
 // ---------------------------------------------------------------------------
 namespace {
 
-constexpr int kDirectBlock = 128;
+constexpr int kDirectBlock = 256;
 
-// LU with partial pivoting of a[NT][NT] in place; perm[i] = original row of
-// row i.  The determinant is returned as mant * 2^ex (mant = 0 if singular).
-template <int NT>
-__device__ __forceinline__ void lu_regs(double (&a)[NT][NT], int (&perm)[NT], double &mant,
+// LU with partial pivoting of a[K][K] in place; with PERM, perm[i] = original
+// row of row i and the multipliers are kept below the diagonal (without PERM
+// only what the determinant needs is updated).  The determinant is returned
+// as mant * 2^ex (mant = 0 if singular).
+template <int K, bool PERM>
+__device__ __forceinline__ void lu_regs(double (&a)[K][K], int (&perm)[K], double &mant,
                                         int &ex) {
+    if constexpr (PERM) {
 #pragma unroll
-    for (int i = 0; i < NT; ++i) perm[i] = i;
+        for (int i = 0; i < K; ++i) perm[i] = i;
+    }
     double m = 1.0;
     int k = 0;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
+    for (int j = 0; j < K; ++j) {
         int p = j;
         double best = fabs(a[j][j]);
 #pragma unroll
-        for (int i = j + 1; i < NT; ++i)
+        for (int i = j + 1; i < K; ++i)
             if (fabs(a[i][j]) > best) {
                 best = fabs(a[i][j]);
                 p = i;
@@ -860,29 +1038,32 @@ __device__ __forceinline__ void lu_regs(double (&a)[NT][NT], int (&perm)[NT], do
             return;
         }
 #pragma unroll
-        for (int i = j + 1; i < NT; ++i)
+        for (int i = j + 1; i < K; ++i)
             if (i == p) {
 #pragma unroll
-                for (int c = 0; c < NT; ++c) {
+                for (int c = PERM ? 0 : j; c < K; ++c) {
                     const double t = a[i][c];
                     a[i][c] = a[j][c];
                     a[j][c] = t;
                 }
-                const int t = perm[i];
-                perm[i] = perm[j];
-                perm[j] = t;
+                if constexpr (PERM) {
+                    const int t = perm[i];
+                    perm[i] = perm[j];
+                    perm[j] = t;
+                }
                 m = -m;
             }
         m *= a[j][j];
         int kk;
         m = frexp(m, &kk);
         k += kk;
+        const double rinv = 1.0 / a[j][j];
 #pragma unroll
-        for (int i = j + 1; i < NT; ++i) {
-            const double l = a[i][j] / a[j][j];
-            a[i][j] = l;
+        for (int i = j + 1; i < K; ++i) {
+            const double l = div_by(a[i][j], a[j][j], rinv);
+            if constexpr (PERM) a[i][j] = l;
 #pragma unroll
-            for (int c = j + 1; c < NT; ++c) a[i][c] -= l * a[j][c];
+            for (int c = j + 1; c < K; ++c) a[i][c] -= l * a[j][c];
         }
     }
     mant = m;
@@ -903,53 +1084,48 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
-}  // namespace
-
-// pass 1: mantissa and exponent of every determinant of the block's range,
-// and the integer maximum of the exponents per (walker, spin)
-template <int NT>
-__global__ void __launch_bounds__(kDirectBlock) k_direct_ratios_t(KernelArgs a, int sp) {
-    const int w = blockIdx.x, part = blockIdx.y;
-    const size_t ws = (size_t)w * 2 + sp;
-    if (a.wk.flag[ws] == 0) return;
-    const SpinDev S = a.sp[sp];
-    const int M = a.M, tid = threadIdx.x;
-    extern __shared__ double lds[];
-    double *P0 = lds;                 // [NT][M] scaled orbital values of this spin
-    int *Ex = (int *)(P0 + NT * M);   // [M]
-    int *occ0 = Ex + M;               // [NT]
-    __shared__ int red[kDirectBlock];
-    const double *phig = a.wk.phi + (size_t)w * a.N * 5 * M;
-    for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[ws * M + m];
-    for (int c = tid; c < NT; c += kDirectBlock) occ0[c] = S.occ0[c];
-    __syncthreads();
-    for (int i = tid; i < NT * M; i += kDirectBlock) {
-        const int e = i / M, m = i - e * M;
-        P0[i] = phig[(size_t)(S.e0 + e) * 5 * M + m] * pow2(-Ex[m]);
+// K x K Slater matrix of determinant D (slots in ascending order) from the
+// staged scaled values P0[e*M + m] of the spin's n <= K electrons, padded
+// with an identity block; occ[c] = orbital of slot c; returns sum of the
+// column exponents.
+template <int K>
+__device__ __forceinline__ int direct_matrix(const DetDesc &D, const int *occ0, const double *P0,
+                                             const int *Ex, int M, int n, double (&A)[K][K],
+                                             int (&occ)[K]) {
+    int sx = 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        occ[c] = (c < n) ? slot_orbital(D, occ0, c) : 0;
+        if (c < n) sx += Ex[occ[c]];
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+            const double v = P0[min(e, n - 1) * M + occ[c]];
+            A[e][c] = (c < n) ? ((e < n) ? v : 0.0) : ((e == c) ? 1.0 : 0.0);
+        }
     }
-    __syncthreads();
+    return sx;
+}
+
+// one work item of the ratio pass: mantissa and exponent of determinants
+// [d0, d1) of (walker w, spin sp); returns the thread's largest exponent
+template <int K>
+__device__ __forceinline__ int direct_ratio_item(const KernelArgs &a, int sp, int w, const SpinDev &S,
+                                 const int *occ0, const double *P0, const int *Ex, int d0,
+                                 int d1) {
+    const int M = a.M, n = S.n;
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
-    const int d0 = (int)((int64_t)S.U * part / a.direct_split);
-    const int d1 = (int)((int64_t)S.U * (part + 1) / a.direct_split);
     int kmax = INT_MIN;
-    for (int d = d0 + tid; d < d1; d += kDirectBlock) {
+    for (int d = d0 + (int)threadIdx.x; d < d1; d += kDirectBlock) {
         const DetDesc D = S.desc[d];
         double r = 0.0;
         int rexp = INT_MIN;
         if (D.s <= dmax) {
-            double A[NT][NT];
-            int perm[NT];
-            int sx = 0;
-#pragma unroll
-            for (int c = 0; c < NT; ++c) {
-                const int o = slot_orbital(D, occ0, c);
-                sx += Ex[o];
-#pragma unroll
-                for (int e = 0; e < NT; ++e) A[e][c] = P0[e * M + o];
-            }
+            double A[K][K];
+            int occ[K], perm[K];
+            const int sx = direct_matrix<K>(D, occ0, P0, Ex, M, n, A, occ);
             double mant;
             int ex;
-            lu_regs<NT>(A, perm, mant, ex);
+            lu_regs<K, false>(A, perm, mant, ex);
             if (mant != 0.0) {
                 r = (double)D.eps * mant;
                 rexp = ex + sx;
@@ -960,131 +1136,207 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_ratios_t(KernelArgs a, 
         a.wk.R64[o] = r;
         a.wk.Rexp[o] = rexp;
     }
-    red[tid] = kmax;
-    __syncthreads();
-    if (tid == 0) {
-        int m = INT_MIN;
-        for (int t = 0; t < kDirectBlock; ++t) m = max(m, red[t]);
-        if (m != INT_MIN) atomicMax(&a.wk.Kmax[ws], m);
+    return kmax;
+}
+
+// one work item of the derivative pass: adds, per electron e and component
+// q, the wave sums of  w_d R_d grad~_e D_d / D_d  (row-replacement form with
+// the columns of S_d^-1) to red[wave][e*4 + q]
+template <int K>
+__device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, int w, const SpinDev &S,
+                                  const int *occ0, const double *P0, const double *Gs,
+                                  const double *Gg, const int *Ex, int d0, int d1,
+                                  double *red) {
+    const int M = a.M, n = S.n, N = a.N;
+    const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
+    const int Kx = a.wk.K[(size_t)w * 2 + sp];
+    const bool mixed = a.precision == MDET_MIXED;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int base = d0; base < d1; base += kDirectBlock) {
+        // every lane takes part in the wave sums; lanes without a valid
+        // determinant contribute zeros
+        const int d = base + (int)threadIdx.x;
+        const bool in = d < d1;
+        const DetDesc D = S.desc[in ? d : d0];
+        const size_t o = rv_index(a, sp, in ? d : d0, w);
+        const int rexp = a.wk.Rexp[o];
+        bool valid = in && D.s <= dmax && rexp != INT_MIN;
+        double A[K][K];
+        int occ[K], perm[K];
+        direct_matrix<K>(D, occ0, P0, Ex, M, n, A, occ);
+        double mant;
+        int ex;
+        lu_regs<K, true>(A, perm, mant, ex);
+        valid = valid && mant != 0.0;
+        const double wt = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
+        const double coef = valid ? wt * ldexp((double)D.eps * mant, rexp - Kx) : 0.0;
+#pragma unroll
+        for (int i = 0; i < K; ++i) A[i][i] = 1.0 / A[i][i];  // U's diagonal, inverted
+#pragma unroll 1
+        for (int e = 0; e < n; ++e) {
+            // column e of S_d^-1
+            double x[K];
+#pragma unroll
+            for (int i = 0; i < K; ++i) x[i] = (perm[i] == e) ? 1.0 : 0.0;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+#pragma unroll
+                for (int j = 0; j < i; ++j) x[i] -= A[i][j] * x[j];
+#pragma unroll
+            for (int i = K - 1; i >= 0; --i) {
+#pragma unroll
+                for (int j = i + 1; j < K; ++j) x[i] -= A[i][j] * x[j];
+                x[i] *= A[i][i];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double s = 0.0;
+                if (Gs) {
+                    const double *G = Gs + (size_t)(q * n + e) * M;
+#pragma unroll
+                    for (int c = 0; c < K; ++c)
+                        if (c < n) s += x[c] * G[occ[c]];
+                } else {
+                    const double *G = Gg + (size_t)e * 5 * M + (size_t)(1 + q) * M;
+#pragma unroll
+                    for (int c = 0; c < K; ++c)
+                        if (c < n) s += x[c] * (G[occ[c]] * pow2(-Ex[occ[c]]));
+                }
+                const double v = wave_sum(valid ? coef * s : 0.0);
+                if (lane == 0) red[wave * 4 * K + e * 4 + q] += v;
+            }
+        }
+    }
+}
+
+// stage the scaled orbital values (and, if G is not null, the derivatives) of
+// electrons e0 .. e0+n-1 of walker w: dst[(q*n + e)*M + m] = phi_q * 2^-E[m]
+__device__ void stage_orbitals(const KernelArgs &a, int w, int e0, int n, const int *Ex,
+                               double *P0, double *G) {
+    const int M = a.M;
+    const double *phig = a.wk.phi + ((size_t)w * a.N + e0) * 5 * M;
+    const int nq = G ? 5 : 1;
+    for (int i = threadIdx.x; i < nq * n * M; i += blockDim.x) {
+        const int q = i / (n * M), r = i - q * n * M, e = r / M, m = r - e * M;
+        const double v = phig[(size_t)e * 5 * M + (size_t)q * M + m] * pow2(-Ex[m]);
+        if (q == 0) P0[r] = v;
+        else G[i - n * M] = v;
+    }
+}
+
+}  // namespace
+
+// pass 1: mantissa and exponent of every determinant of the flagged pairs,
+// and the integer maximum of the exponents per (walker, spin)
+template <int NT>
+__global__ void __launch_bounds__(kDirectBlock) k_direct_ratios_t(KernelArgs a) {
+    const int M = a.M, tid = threadIdx.x, split = a.direct_split;
+    extern __shared__ double lds[];
+    double *P0 = lds;                 // [NT][M] scaled orbital values of the pair's spin
+    int *Ex = (int *)(P0 + NT * M);   // [M]
+    int *occ0 = Ex + M;               // [NT]
+    __shared__ int red[kDirectBlock];
+    const int nitems = a.wk.dcount[0] * split;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int ws = __builtin_amdgcn_readfirstlane(a.wk.dlist[it / split]);
+        const int part = it - (it / split) * split;
+        const int w = ws >> 1, sp = ws & 1;
+        const SpinDev &S = a.sp[sp];
+        const int n = S.n;
+        __syncthreads();  // the previous item is done with the LDS
+        for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[(size_t)ws * M + m];
+        for (int c = tid; c < n; c += kDirectBlock) occ0[c] = S.occ0[c];
+        __syncthreads();
+        stage_orbitals(a, w, S.e0, n, Ex, P0, nullptr);
+        __syncthreads();
+        const int d0 = (int)((int64_t)S.U * part / split);
+        const int d1 = (int)((int64_t)S.U * (part + 1) / split);
+        int kmax;
+        if (NT > 1 && n == NT - 1)
+            kmax = direct_ratio_item<(NT > 1 ? NT - 1 : 1)>(a, sp, w, S, occ0, P0, Ex, d0, d1);
+        else kmax = direct_ratio_item<NT>(a, sp, w, S, occ0, P0, Ex, d0, d1);  // n <= NT
+        red[tid] = kmax;
+        __syncthreads();
+        if (tid == 0) {
+            int mx = INT_MIN;
+            for (int t = 0; t < kDirectBlock; ++t) mx = max(mx, red[t]);
+            if (mx != INT_MIN) atomicMax(&a.wk.Kmax[ws], mx);
+        }
     }
 }
 
 // pass 2: shift every ratio by the (walker, spin) maximum exponent
 __global__ void __launch_bounds__(kBlock) k_direct_scale(KernelArgs a) {
-    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, part = blockIdx.y;
-    const size_t ws = (size_t)w * 2 + sp;
-    if (a.wk.flag[ws] == 0) return;
-    const SpinDev S = a.sp[sp];
-    int K = a.wk.Kmax[ws];
-    if (K == INT_MIN) K = 0;
-    if (part == 0 && threadIdx.x == 0) {
-        a.wk.K[ws] = K;
-        a.wk.logdet0[ws] = 0.0;
-        a.wk.sign0[ws] = 1.0;
-    }
-    const int d0 = (int)((int64_t)S.U * part / a.direct_split);
-    const int d1 = (int)((int64_t)S.U * (part + 1) / a.direct_split);
-    for (int d = d0 + threadIdx.x; d < d1; d += kBlock) {
-        const size_t o = rv_index(a, sp, d, w);
-        const int e = a.wk.Rexp[o];
-        const double r = (e == INT_MIN) ? 0.0 : ldexp(a.wk.R64[o], e - K);
-        if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
-        else a.wk.R64[o] = r;
+    const int split = a.direct_split;
+    const int nitems = a.wk.dcount[0] * split;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int ws = __builtin_amdgcn_readfirstlane(a.wk.dlist[it / split]);
+        const int part = it - (it / split) * split;
+        const int w = ws >> 1, sp = ws & 1;
+        const SpinDev &S = a.sp[sp];
+        int K = a.wk.Kmax[ws];
+        if (K == INT_MIN) K = 0;
+        if (part == 0 && threadIdx.x == 0) {
+            a.wk.K[ws] = K;
+            a.wk.logdet0[ws] = 0.0;
+            a.wk.sign0[ws] = 1.0;
+        }
+        const int d0 = (int)((int64_t)S.U * part / split);
+        const int d1 = (int)((int64_t)S.U * (part + 1) / split);
+        for (int d = d0 + threadIdx.x; d < d1; d += kBlock) {
+            const size_t o = rv_index(a, sp, d, w);
+            const int e = a.wk.Rexp[o];
+            const double r = (e == INT_MIN) ? 0.0 : ldexp(a.wk.R64[o], e - K);
+            if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
+            else a.wk.R64[o] = r;
+        }
     }
 }
 
-// derivatives: partial sums over the block's determinants of
-// w_d R_d grad~_e D_d / D_d (row-replacement form, columns of S_d^-1)
+// pass 3 (after the sparse combination): derivative partial sums per item
 template <int NT>
-__global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a, int sp) {
-    const int w = blockIdx.x, part = blockIdx.y;
-    const size_t ws = (size_t)w * 2 + sp;
-    if (a.wk.flag[ws] == 0) return;
-    const SpinDev S = a.sp[sp];
-    const int M = a.M, N = a.N, tid = threadIdx.x;
+__global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a) {
+    const int M = a.M, N = a.N, tid = threadIdx.x, split = a.direct_split;
+    const bool stage_g = a.direct_stage_grad != 0;
     extern __shared__ double lds[];
-    double *P = lds;                    // [5][NT][M] scaled orbitals and derivatives
-    double *red = P + 5 * NT * M;       // [kDirectBlock / 64][NT * 4]
+    double *P0 = lds;                                  // [NT][M] scaled values
+    double *G = stage_g ? P0 + NT * M : nullptr;       // [4][NT][M] scaled derivatives
+    double *red = P0 + (stage_g ? 5 : 1) * NT * M;     // [kDirectBlock / 64][NT * 4]
     int *Ex = (int *)(red + (kDirectBlock / 64) * NT * 4);  // [M]
-    int *occ0 = Ex + M;                 // [NT]
-    const double *phig = a.wk.phi + (size_t)w * N * 5 * M;
-    for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[ws * M + m];
-    for (int c = tid; c < NT; c += kDirectBlock) occ0[c] = S.occ0[c];
-    __syncthreads();
-    for (int i = tid; i < 5 * NT * M; i += kDirectBlock) {
-        const int q = i / (NT * M), r = i - q * NT * M, e = r / M, m = r - e * M;
-        P[i] = phig[(size_t)(S.e0 + e) * 5 * M + (size_t)q * M + m] * pow2(-Ex[m]);
-    }
-    __syncthreads();
-    const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
-    const int K = a.wk.K[ws];
-    const bool mixed = a.precision == MDET_MIXED;
-    const int d0 = (int)((int64_t)S.U * part / a.direct_split);
-    const int d1 = (int)((int64_t)S.U * (part + 1) / a.direct_split);
-    double acc[NT][4];
-#pragma unroll
-    for (int e = 0; e < NT; ++e)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[e][q] = 0.0;
-    for (int d = d0 + tid; d < d1; d += kDirectBlock) {
-        const DetDesc D = S.desc[d];
-        if (D.s > dmax) continue;
-        const size_t o = rv_index(a, sp, d, w);
-        const int rexp = a.wk.Rexp[o];
-        if (rexp == INT_MIN) continue;
-        double A[NT][NT];
-        int perm[NT], occ[NT];
-#pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            occ[c] = slot_orbital(D, occ0, c);
-#pragma unroll
-            for (int e = 0; e < NT; ++e) A[e][c] = P[e * M + occ[c]];
+    int *occ0 = Ex + M;                                // [NT]
+    const int nitems = a.wk.dcount[0] * split;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int ws = __builtin_amdgcn_readfirstlane(a.wk.dlist[it / split]);
+        const int part = it - (it / split) * split;
+        const int w = ws >> 1, sp = ws & 1;
+        const SpinDev &S = a.sp[sp];
+        const int n = S.n;
+        __syncthreads();  // the previous item is done with the LDS
+        for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[(size_t)ws * M + m];
+        for (int c = tid; c < n; c += kDirectBlock) occ0[c] = S.occ0[c];
+        for (int i = tid; i < (kDirectBlock / 64) * NT * 4; i += kDirectBlock) red[i] = 0.0;
+        __syncthreads();
+        stage_orbitals(a, w, S.e0, n, Ex, P0, G);
+        __syncthreads();
+        const double *Gg = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
+        const int d0 = (int)((int64_t)S.U * part / split);
+        const int d1 = (int)((int64_t)S.U * (part + 1) / split);
+        int K;
+        if (NT > 1 && n == NT - 1) {
+            K = NT > 1 ? NT - 1 : 1;
+            direct_deriv_item<(NT > 1 ? NT - 1 : 1)>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1,
+                                                      red);
+        } else {
+            K = NT;  // n <= NT
+            direct_deriv_item<NT>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1, red);
         }
-        double mant;
-        int ex;
-        lu_regs<NT>(A, perm, mant, ex);
-        if (mant == 0.0) continue;
-        const double wt = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
-        const double coef = wt * ldexp((double)D.eps * mant, rexp - K);
-        // column e of S_d^-1: solve S x = e_e; grad~_e D_d / D_d = sum_c x_c G_q[e][occ_c]
-#pragma unroll
-        for (int e = 0; e < NT; ++e) {
-            double x[NT];
-#pragma unroll
-            for (int i = 0; i < NT; ++i) x[i] = (perm[i] == e) ? 1.0 : 0.0;
-#pragma unroll
-            for (int i = 0; i < NT; ++i)
-#pragma unroll
-                for (int j = 0; j < i; ++j) x[i] -= A[i][j] * x[j];
-#pragma unroll
-            for (int i = NT - 1; i >= 0; --i) {
-#pragma unroll
-                for (int j = i + 1; j < NT; ++j) x[i] -= A[i][j] * x[j];
-                x[i] /= A[i][i];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const double *Gq = P + (size_t)(1 + q) * NT * M + e * M;
-                double s = 0.0;
-#pragma unroll
-                for (int c = 0; c < NT; ++c) s += x[c] * Gq[occ[c]];
-                acc[e][q] += coef * s;
-            }
+        __syncthreads();
+        for (int i = tid; i < n * 4; i += kDirectBlock) {
+            const int e = i >> 2, q = i & 3;
+            double t = 0.0;
+            for (int v = 0; v < kDirectBlock / 64; ++v) t += red[v * 4 * K + e * 4 + q];
+            a.wk.dpart[(((size_t)w * kDirectSplitMax + part) * N + S.e0) * 4 + i] = t;
         }
-    }
-    const int wave = tid >> 6, lane = tid & 63;
-#pragma unroll
-    for (int e = 0; e < NT; ++e)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double v = wave_sum(acc[e][q]);
-            if (lane == 0) red[wave * NT * 4 + e * 4 + q] = v;
-        }
-    __syncthreads();
-    for (int i = tid; i < NT * 4; i += kDirectBlock) {
-        double t = 0.0;
-        for (int v = 0; v < kDirectBlock / 64; ++v) t += red[v * NT * 4 + i];
-        a.wk.dpart[(((size_t)w * kDirectSplitMax + part) * N + S.e0) * 4 + i] = t;
     }
 }
 
@@ -1093,33 +1345,37 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a, i
 // combined here; nodes get zero derivatives.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a) {
-    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (w >= a.W) return;
+    // one thread per output entry (walker w, electron e, component q); the
+    // thread with e = q = 0 also writes the walker's sign, ln|Psi| and status
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int per = 4 * a.N;
+    if (i >= a.W * per) return;
+    const int64_t w = i / per;
+    const int t = (int)(i - w * per);
     const double psi = psi_value(a, (int)w);
-    const int f0 = a.wk.flag[2 * w], f1 = a.wk.flag[2 * w + 1];
     const bool node = !(psi != 0.0) || !isfinite(psi);
+    const int sp = (t >= 4 * a.sp[1].e0) ? 1 : 0;
+    if (node) {
+        a.gl_out[i] = 0.0;
+    } else if (a.wk.flag[2 * w + sp] != 0) {
+        double s = 0.0;
+        for (int p = 0; p < a.direct_split; ++p)
+            s += a.wk.dpart[((size_t)w * kDirectSplitMax + p) * per + t];
+        a.gl_out[i] = s / psi;
+    }
+    if (t != 0) return;
     if (node) {
         a.sign_out[w] = 0.0;
         a.logabs_out[w] = -INFINITY;
-        for (int t = 0; t < 4 * a.N; ++t) a.gl_out[w * 4 * a.N + t] = 0.0;
         if (a.wstatus) a.wstatus[w] = MDET_W_NODE;
         return;
-    }
-    for (int sp = 0; sp < 2; ++sp) {
-        if (a.wk.flag[2 * w + sp] == 0) continue;
-        const int e0 = a.sp[sp].e0, n = a.sp[sp].n;
-        for (int t = 4 * e0; t < 4 * (e0 + n); ++t) {
-            double s = 0.0;
-            for (int p = 0; p < a.direct_split; ++p)
-                s += a.wk.dpart[((size_t)w * kDirectSplitMax + p) * a.N * 4 + t];
-            a.gl_out[w * 4 * a.N + t] = s / psi;
-        }
     }
     const double sg = a.wk.sign0[2 * w] * a.wk.sign0[2 * w + 1] * (psi > 0 ? 1.0 : -1.0);
     a.sign_out[w] = sg;
     a.logabs_out[w] = a.wk.logdet0[2 * w] + a.wk.logdet0[2 * w + 1] + log(fabs(psi)) +
                       (double)(a.wk.K[2 * w] + a.wk.K[2 * w + 1]) * 0.69314718055994530942;
-    if (a.wstatus) a.wstatus[w] = (f0 || f1) ? MDET_W_FALLBACK : MDET_W_OK;
+    if (a.wstatus)
+        a.wstatus[w] = (a.wk.flag[2 * w] || a.wk.flag[2 * w + 1]) ? MDET_W_FALLBACK : MDET_W_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1203,40 +1459,48 @@ __global__ void __launch_bounds__(256) k_sort_scatter(int64_t W, int N, const in
 namespace {
 
 template <int NT>
-void launch_direct(const KernelArgs &a, hipStream_t st, int sp, bool deriv) {
-    const int M = a.M, W = (int)a.W;
-    const dim3 grid(W, a.direct_split);
+void launch_direct(const KernelArgs &a, hipStream_t st, bool deriv) {
+    const int M = a.M;
+    // a fixed grid walks the (pair, part) items; at most 2 W of them per part
+    const unsigned grid = (unsigned)std::min<int64_t>(2 * a.W * a.direct_split, 1024);
     if (deriv) {
-        const size_t lds = sizeof(double) * (5 * (size_t)NT * M + (kDirectBlock / 64) * NT * 4) +
+        const size_t lds = sizeof(double) * ((a.direct_stage_grad ? 5 : 1) * (size_t)NT * M +
+                                             (kDirectBlock / 64) * NT * 4) +
                            sizeof(int) * (M + NT);
-        k_direct_deriv_t<NT><<<grid, dim3(kDirectBlock), lds, st>>>(a, sp);
+        k_direct_deriv_t<NT><<<dim3(grid), dim3(kDirectBlock), lds, st>>>(a);
     } else {
         const size_t lds = sizeof(double) * (size_t)NT * M + sizeof(int) * (M + NT);
-        k_direct_ratios_t<NT><<<grid, dim3(kDirectBlock), lds, st>>>(a, sp);
+        k_direct_ratios_t<NT><<<dim3(grid), dim3(kDirectBlock), lds, st>>>(a);
     }
 }
 
 void launch_direct_n(const KernelArgs &a, hipStream_t st, bool deriv) {
-    for (int sp = 0; sp < 2; ++sp) {
-        switch (a.sp[sp].n) {
-        case 1: launch_direct<1>(a, st, sp, deriv); break;
-        case 2: launch_direct<2>(a, st, sp, deriv); break;
-        case 3: launch_direct<3>(a, st, sp, deriv); break;
-        case 4: launch_direct<4>(a, st, sp, deriv); break;
-        case 5: launch_direct<5>(a, st, sp, deriv); break;
-        case 6: launch_direct<6>(a, st, sp, deriv); break;
-        case 7: launch_direct<7>(a, st, sp, deriv); break;
-        case 8: launch_direct<8>(a, st, sp, deriv); break;
-        case 9: launch_direct<9>(a, st, sp, deriv); break;
-        case 10: launch_direct<10>(a, st, sp, deriv); break;
-        case 11: launch_direct<11>(a, st, sp, deriv); break;
-        case 12: launch_direct<12>(a, st, sp, deriv); break;
-        case 13: launch_direct<13>(a, st, sp, deriv); break;
-        case 14: launch_direct<14>(a, st, sp, deriv); break;
-        case 15: launch_direct<15>(a, st, sp, deriv); break;
-        default: launch_direct<16>(a, st, sp, deriv); break;  // n <= MDET_MAX_SPIN_ELEC = 16
-        }
+    switch (a.nmax) {  // the larger electron count (n_up)
+    case 1: launch_direct<1>(a, st, deriv); break;
+    case 2: launch_direct<2>(a, st, deriv); break;
+    case 3: launch_direct<3>(a, st, deriv); break;
+    case 4: launch_direct<4>(a, st, deriv); break;
+    case 5: launch_direct<5>(a, st, deriv); break;
+    case 6: launch_direct<6>(a, st, deriv); break;
+    case 7: launch_direct<7>(a, st, deriv); break;
+    case 8: launch_direct<8>(a, st, deriv); break;
+    case 9: launch_direct<9>(a, st, deriv); break;
+    case 10: launch_direct<10>(a, st, deriv); break;
+    case 11: launch_direct<11>(a, st, deriv); break;
+    case 12: launch_direct<12>(a, st, deriv); break;
+    case 13: launch_direct<13>(a, st, deriv); break;
+    case 14: launch_direct<14>(a, st, deriv); break;
+    case 15: launch_direct<15>(a, st, deriv); break;
+    default: launch_direct<16>(a, st, deriv); break;  // nmax <= MDET_MAX_SPIN_ELEC = 16
     }
+}
+
+// slices per flagged pair of the fallback: one determinant per thread up to
+// kDirectSplitMax slices, unless requested explicitly
+int direct_splits(const KernelArgs &a, int requested) {
+    if (requested > 0) return std::max(1, std::min(requested, kDirectSplitMax));
+    const int U = std::max(a.sp[0].U, a.sp[1].U);
+    return std::max(1, std::min((U + kDirectBlock - 1) / kDirectBlock, kDirectSplitMax));
 }
 
 int psi_splits(int64_t W, int requested) {
@@ -1255,7 +1519,9 @@ hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
     if (W == 0) return hipSuccess;
     KernelArgs a = args;
     a.psi_nparts = psi_splits(W, a.cfg.spmm_rsplit);
-    a.direct_split = std::max(1, std::min((int)a.cfg.direct_split, kDirectSplitMax));
+    a.direct_split = direct_splits(a, a.cfg.direct_split);
+    // stage the orbital derivatives of the fallback in LDS when they fit
+    a.direct_stage_grad = sizeof(double) * (5 * (size_t)a.nmax * a.M) <= 96 * 1024 ? 1 : 0;
     if (!(a.max_degree && a.cfg.sort_walkers)) return launch_core(a, st, ev);
     // uneven batch: evaluate the walkers in ascending order of maximum degree
     const int N = a.N;
@@ -1287,33 +1553,36 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[k], st);
     };
     mark(0);
-    size_t lds_ref = sizeof(double) * ((size_t)n * M + M + 3 * n * n) + sizeof(int) * M;
-    k_reference<<<g2, blk, lds_ref, st>>>(a);
+    const size_t prim_bytes = (size_t)M * a.P * sizeof(Prim);
+    const size_t lds_ref = sizeof(double) * (14 * (size_t)n * n + (size_t)a.N * (3 * kPowLd + 1)) +
+                           sizeof(int) * 4 * (size_t)M + (prim_bytes <= kPrimLdsMax ? prim_bytes : 0);
+    k_reference<<<dim3(W), blk, lds_ref, st>>>(a);
     mark(1);
-    size_t lds_rat = sizeof(double) * (size_t)n * M + sizeof(int) * (M + n);
+    const size_t lds_rat = sizeof(double) * ((size_t)n * M + n * n) + sizeof(int) * (M + n);
     k_ratios<<<g2, blk, lds_rat, st>>>(a);
     mark(2);
     launch_direct_n(a, st, false);
-    k_direct_scale<<<dim3(2 * W, a.direct_split), blk, 0, st>>>(a);
+    k_direct_scale<<<dim3((unsigned)std::min<int64_t>(2 * (int64_t)W * a.direct_split, 1024)),
+                     blk, 0, st>>>(a);
     mark(3);
     const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
-    const dim3 gs(tiles * a.psi_nparts, 2), bs(64 * kSpmmWaves);
+    const dim3 gs((tiles + 7) / 8 * 8 * a.psi_nparts, 2), bs(64 * kSpmmWaves);
     if (a.precision == MDET_MIXED)
-        k_spmm<float, kSpmmCols32, true><<<gs, bs, 0, st>>>(
-            a, a.wk.R32, a.wk.uv32, a.C.rval32, a.C.cval32, a.C.rcol, a.C.crow, a.C.rseg32,
+        k_spmm<float, kSpmmCols32><<<gs, bs, 0, st>>>(
+            a, a.wk.R32, a.wk.uv32, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg32,
             a.C.cseg32, a.C.nch_r32, a.C.nch_c32, a.psi_nparts);
     else
-        k_spmm<double, kSpmmCols64, false><<<gs, bs, 0, st>>>(
+        k_spmm<double, kSpmmCols64><<<gs, bs, 0, st>>>(
             a, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
             a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
     mark(4);
-    size_t lds_der = sizeof(double) * (3 * (size_t)n * M + 2 * n * n + kAdjChunk) +
-                     sizeof(int) * (M + n);
+    const size_t lds_der = sizeof(double) * (3 * (size_t)n * M + 2 * n * n + kAdjChunk) +
+                           sizeof(int) * (M + n + (size_t)n * M + 1) + sizeof(uint16_t) * kAdjChunk;
     k_deriv<<<g2, blk, lds_der, st>>>(a);
     mark(5);
     launch_direct_n(a, st, true);
     mark(6);
-    k_finalize<<<dim3((W + kBlock - 1) / kBlock), blk, 0, st>>>(a);
+    k_finalize<<<dim3((unsigned)(((int64_t)W * 4 * a.N + kBlock - 1) / kBlock)), blk, 0, st>>>(a);
     mark(7);
     return hipGetLastError();
 }
