@@ -97,6 +97,7 @@ struct mdet_ctx {
     int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
     LaunchCfg cfg{0, 0, 1};
     hipStream_t own_stream = nullptr;
+
     // captured evaluations (mdet_eval_graph), keyed by every argument
     struct GraphEntry {
         int64_t W;
@@ -114,21 +115,23 @@ struct mdet_ctx {
     }
     double prep_seconds = 0.0;
     double kappa_max = 3e4;
-    // optional per-kernel timing with HIP events on the caller's stream: a
-    // ring of event sets, harvested when the ring wraps or on request
+    // optional per-kernel timing with HIP events (a start and an end event
+    // per kernel, on the stream it runs on): a ring of event sets, harvested
+    // when the ring wraps or on request
     static constexpr int kRing = 64;
+    static constexpr int kSetEvents = 2 * kNumKernels;
     bool profiling = false;
-    std::vector<hipEvent_t> prof_ev;  // [kRing][kNumKernels + 1]
+    std::vector<hipEvent_t> prof_ev;  // [kRing][kSetEvents]
     int prof_head = 0, prof_pending = 0;
     double prof_ms[kNumKernels] = {0};
     int64_t prof_calls = 0;
     void harvest_one() {  // oldest pending set
         const int slot = (prof_head - prof_pending + kRing) % kRing;
-        hipEvent_t *e = &prof_ev[(size_t)slot * (kNumKernels + 1)];
-        (void)hipEventSynchronize(e[kNumKernels]);
+        hipEvent_t *e = &prof_ev[(size_t)slot * kSetEvents];
+        (void)hipEventSynchronize(e[kSetEvents - 1]);  // the last kernel
         for (int k = 0; k < kNumKernels; ++k) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, e[k], e[k + 1]) == hipSuccess) prof_ms[k] += ms;
+            if (hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]) == hipSuccess) prof_ms[k] += ms;
         }
         ++prof_calls;
         --prof_pending;
@@ -138,7 +141,7 @@ struct mdet_ctx {
     }
     hipEvent_t *next_event_set() {
         if (prof_pending == kRing) harvest_one();
-        hipEvent_t *e = &prof_ev[(size_t)prof_head * (kNumKernels + 1)];
+        hipEvent_t *e = &prof_ev[(size_t)prof_head * kSetEvents];
         prof_head = (prof_head + 1) % kRing;
         ++prof_pending;
         return e;
@@ -349,13 +352,15 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
     }
     // Derivative aggregation: the s*s scaled adjugate entries of determinant d
     // occupy slots adj_off[d] + a*s + b of a staging buffer; determinants are
-    // cut into chunks whose slots fit kAdjChunk; per chunk, every target
+    // cut into chunks of at most kAdjChunkDets determinants whose slots fit
+    // kAdjChunk; per chunk, every target
     // t = h[a]*M + p[b] gets the list of its slots (in determinant order).
     s.adj_off.assign(s.U + 1, 0);
     for (int64_t e = 0; e < s.U; ++e) s.adj_off[e + 1] = s.adj_off[e] + s.desc[e].s * s.desc[e].s;
     s.chunk_det.assign(1, 0);
     for (int64_t e = 0; e < s.U; ++e)
-        if (s.adj_off[e + 1] - s.adj_off[s.chunk_det.back()] > kAdjChunk)
+        if (s.adj_off[e + 1] - s.adj_off[s.chunk_det.back()] > kAdjChunk ||
+            e - s.chunk_det.back() >= kAdjChunkDets)
             s.chunk_det.push_back((int32_t)e);
     s.chunk_det.push_back((int32_t)s.U);
     const int nchunk = (int)s.chunk_det.size() - 1;
@@ -896,7 +901,7 @@ mdet_status mdet_set_profiling(mdet_ctx *ctx, int32_t enable) {
         HIP_OK(hipSetDevice(ctx->device));
         ctx->harvest_all();
         if (enable && ctx->prof_ev.empty()) {
-            ctx->prof_ev.assign((size_t)mdet_ctx::kRing * (kNumKernels + 1), nullptr);
+            ctx->prof_ev.assign((size_t)mdet_ctx::kRing * mdet_ctx::kSetEvents, nullptr);
             for (auto &e : ctx->prof_ev) HIP_OK(hipEventCreate(&e));
         }
         ctx->profiling = enable != 0;

@@ -36,6 +36,9 @@ static_assert(sizeof(DetDesc) == 16, "DetDesc layout");
 // Capacity (doubles) of the LDS staging buffer that holds the scaled
 // adjugates of one chunk of determinants during the derivative aggregation.
 constexpr int kAdjChunk = 2048;
+// Largest number of determinants in one such chunk (two per thread of the
+// 256-thread derivative block).
+constexpr int kAdjChunkDets = 512;
 // Sparse combination: a tile of 64 walkers (one per lane) stages the
 // gathered vector in LDS by chunks of kSpmmCols64 (FP64) or kSpmmCols32
 // (FP32) entries, 130 KB either way (row pitch 65).
@@ -149,8 +152,8 @@ constexpr int kNumKernels = 7;
 const char *kernel_name(int k);
 
 // Launch the whole evaluation on `stream`; returns hipSuccess or the first
-// error.  If `events` is not null, events[0..kNumKernels] are recorded on the
-// stream before the first kernel and after each kernel.
+// error.  If `events` is not null, events[2k] and events[2k + 1] are recorded
+// on the stream before and after kernel k (k < kNumKernels).
 hipError_t launch_eval(const KernelArgs &a, hipStream_t stream, hipEvent_t *events);
 
 // ---------------------------------------------------------------- VMC and MLP

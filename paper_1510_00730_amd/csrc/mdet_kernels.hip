@@ -31,6 +31,7 @@ namespace mdet {
 namespace {
 
 constexpr int kBlock = 256;
+static_assert(kAdjChunkDets % kBlock == 0, "whole determinants per thread and chunk");
 constexpr int kMaxN = MDET_MAX_SPIN_ELEC;
 
 __device__ __forceinline__ double pow2(int k) { return ldexp(1.0, k); }
@@ -45,17 +46,35 @@ __device__ __forceinline__ double pow2(int k) { return ldexp(1.0, k); }
 // (no 0 * inf at a coordinate 0); r2 = |r|^2.
 constexpr int kPowLd = 9;
 constexpr size_t kPrimLdsMax = 32 * 1024;  // LDS for the primitives in the orbital kernel
+constexpr size_t kPrimLdsBytes = 2 * sizeof(double) + sizeof(int);  // per primitive
 
-__device__ __forceinline__ void orbital5_tab(const Prim *prim, int P, int m, const double *pw,
-                                             double r2, double out[5]) {
+template <bool STAGED>
+__device__ __forceinline__ void orbital5_tab(const Prim *prim, const double *s_al,
+                                             const double *s_cf, const int *s_abc, int P, int M,
+                                             int m, const double *pw, double r2, double out[5]) {
     double v = 0, gx = 0, gy = 0, gz = 0, lap = 0;
     for (int p = 0; p < P; ++p) {
-        const Prim q = prim[m * P + p];
-        if (q.coef == 0.0) continue;
-        const double g = q.coef * exp(-q.alpha * r2);
-        const double t2 = 2.0 * q.alpha, t4 = t2 * t2;
+        double alpha, coef;
+        int pa[3];
+        if constexpr (STAGED) {
+            alpha = s_al[p * M + m];
+            coef = s_cf[p * M + m];
+            const int abc = s_abc[p * M + m];
+            pa[0] = abc & 255;
+            pa[1] = (abc >> 8) & 255;
+            pa[2] = abc >> 16;
+        } else {
+            const Prim q = prim[m * P + p];
+            alpha = q.alpha;
+            coef = q.coef;
+            pa[0] = q.a;
+            pa[1] = q.b;
+            pa[2] = q.c;
+        }
+        if (coef == 0.0) continue;
+        const double g = coef * exp(-alpha * r2);
+        const double t2 = 2.0 * alpha, t4 = t2 * t2;
         double f[3][3];
-        const int pa[3] = {q.a, q.b, q.c};
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
             const double *P0 = pw + ax * kPowLd + 2 + pa[ax];
@@ -442,12 +461,20 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     int *slot = emax + 2 * M;         // [2][M] reference slot of orbital m, or -1
     double *pw = (double *)(slot + 2 * M);  // [N][3][kPowLd] coordinate powers
     double *r2s = pw + N * 3 * kPowLd;      // [N] |r|^2
-    // the primitives, staged when they fit (else read from HBM)
-    const bool stage_prim = (size_t)M * a.P * sizeof(Prim) <= kPrimLdsMax;
-    Prim *prl = (Prim *)(r2s + N);
-    const Prim *prim = stage_prim ? prl : a.prim;
+    // the primitives, staged as [p][m] arrays when they fit (else read from
+    // HBM): consecutive orbitals in consecutive LDS words
+    const int MP = M * a.P;
+    const bool stage_prim = (size_t)MP * kPrimLdsBytes <= kPrimLdsMax;
+    double *p_al = r2s + N, *p_cf = p_al + MP;
+    int *p_abc = (int *)(p_cf + MP);
     if (stage_prim)
-        for (int i = tid; i < M * a.P; i += kBlock) prl[i] = a.prim[i];
+        for (int i = tid; i < MP; i += kBlock) {
+            const int m = i / a.P, p = i - m * a.P;
+            const Prim q = a.prim[i];
+            p_al[p * M + m] = q.alpha;
+            p_cf[p * M + m] = q.coef;
+            p_abc[p * M + m] = q.a | (q.b << 8) | (q.c << 16);
+        }
 
     if (w == 0 && tid == 0) a.wk.dcount[0] = 0;  // fallback list, filled by k_ratios
     for (int i = tid; i < 2 * M; i += kBlock) {
@@ -481,7 +508,10 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     for (int idx = tid; idx < N * M; idx += kBlock) {
         const int e = idx / M, m = idx - e * M;
         double o[5];
-        orbital5_tab(prim, a.P, m, pw + e * 3 * kPowLd, r2s[e], o);
+        if (stage_prim) orbital5_tab<true>(nullptr, p_al, p_cf, p_abc, a.P, M, m,
+                                           pw + e * 3 * kPowLd, r2s[e], o);
+        else orbital5_tab<false>(a.prim, nullptr, nullptr, nullptr, a.P, M, m,
+                                 pw + e * 3 * kPowLd, r2s[e], o);
         double *dst = phig + (size_t)e * 5 * M + m;
 #pragma unroll
         for (int q = 0; q < 5; ++q) dst[q * M] = o[q];
@@ -885,6 +915,20 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
 // scaled adjugates w_d f_d adj(M_d) are staged in LDS, then every target
 // (slot c, orbital m) sums its slots in a fixed order into Gamma[c][m].
 // ---------------------------------------------------------------------------
+// LDS layout of k_deriv: T [n][M], X [n][n], Gam [n][M], then a region used
+// first by the chunk loop (adjugates cb [kAdjChunk], gather pointers
+// [n*M + 1], gather positions [kAdjChunk]) and afterwards by Y [M][n],
+// Zc [n][n] and kDerivScratch partial sums; then Ex [M] and occ0 [n].
+constexpr int kDerivScratch = 256;
+constexpr int kGpReg = 4;                   // gather pointers per thread held in registers
+constexpr int kGqReg = kAdjChunk / 256;     // gather positions per thread (all of them)
+
+__host__ __device__ inline size_t deriv_union_doubles(int n, int M) {
+    const size_t loop = kAdjChunk + ((size_t)n * M + 1 + 1) / 2 + kAdjChunk / 4 + 1;
+    const size_t tail = (size_t)M * n + (size_t)n * n + kDerivScratch;
+    return loop > tail ? loop : tail;
+}
+
 __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
     const size_t ws = (size_t)w * 2 + sp;
@@ -896,13 +940,15 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     double *T = lds;                  // [n][M]
     double *X = T + nt;               // [n][n]
     double *Gam = X + n * n;          // [n][M]  Gamma[c][m]
-    double *Y = Gam + nt;             // [M][n]
-    double *Zc = Y + nt;              // [n][n]
-    double *cb = Zc + n * n;          // [kAdjChunk] staged adjugates (later: partial sums)
-    int *Ex = (int *)(cb + kAdjChunk); // [M]
+    double *un = Gam + nt;            // union region
+    double *cb = un;                  // [kAdjChunk] staged adjugates
+    int *gpl = (int *)(cb + kAdjChunk);           // [n*M + 1] the chunk's gather pointers
+    uint16_t *gpo = (uint16_t *)(gpl + nt + 1);   // [kAdjChunk] the chunk's gather positions
+    double *Y = un;                   // [M][n]   (after the chunk loop)
+    double *Zc = Y + (size_t)M * n;   // [n][n]
+    double *scr = Zc + n * n;         // [kDerivScratch]
+    int *Ex = (int *)(un + deriv_union_doubles(n, M));  // [M]
     int *occ0 = Ex + M;               // [n]
-    int *gpl = occ0 + n;              // [n*M + 1] the chunk's gather pointers
-    uint16_t *gpo = (uint16_t *)(gpl + nt + 1);  // [kAdjChunk] the chunk's gather positions
     for (int i = tid; i < nt; i += kBlock) Gam[i] = 0.0;
     const double *Xg = a.wk.X + ws * a.nmax * a.nmax;
     for (int i = tid; i < n * n; i += kBlock) X[i] = Xg[i];
@@ -914,25 +960,73 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
     const int K = a.wk.K[ws];
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const bool mixed = a.precision == MDET_MIXED;
-    for (int k = 0; k < S.nchunk; ++k) {
-        const int d0 = S.chunk_det[k], d1 = S.chunk_det[k + 1];
-        const int base = S.adj_off[d0];
-        // the chunk's gather lists, copied to LDS while the adjugates are staged
+    // a chunk holds at most kDetsPerThread * kBlock determinants: thread tid
+    // takes the chunk's determinants tid + j * kBlock.  Their descriptors and
+    // weights and the thread's share of the chunk's gather lists are fetched
+    // one chunk ahead (registers).
+    constexpr int kDetsPerThread = kAdjChunkDets / kBlock;
+    DetDesc Dc[kDetsPerThread];
+    double wc[kDetsPerThread];
+    int oc[kDetsPerThread];
+    int gpr[kGpReg];
+    uint16_t gqr[kGqReg];
+    auto fetch = [&](int k) {
+        const int dk = S.chunk_det[k], d1 = S.chunk_det[k + 1];
+        const int base = S.adj_off[dk];
+#pragma unroll
+        for (int j = 0; j < kDetsPerThread; ++j) {
+            const int d = dk + tid + j * kBlock;
+            Dc[j].s = 0;
+            wc[j] = 0.0;
+            oc[j] = 0;
+            if (d < d1) {
+                Dc[j] = S.desc[d];
+                oc[j] = S.adj_off[d] - base;
+                if (Dc[j].s <= dmax) {
+                    const size_t o = rv_index(a, sp, d, w);
+                    wc[j] = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
+                }
+            }
+        }
         const int32_t *gp = S.gptr + (size_t)k * (nt + 1);
         const int q0 = gp[0], nq = S.adj_off[d1] - base;
-        for (int t = tid; t <= nt; t += kBlock) gpl[t] = gp[t] - q0;
-        for (int q = tid; q < nq; q += kBlock) gpo[q] = S.gpos[q0 + q];
-        for (int d = d0 + tid; d < d1; d += kBlock) {
-            const DetDesc D = S.desc[d];
+#pragma unroll
+        for (int j = 0; j < kGpReg; ++j) {
+            const int t = tid + j * kBlock;
+            gpr[j] = 0;
+            if (t <= nt) gpr[j] = gp[t] - q0;
+        }
+#pragma unroll
+        for (int j = 0; j < kGqReg; ++j) {
+            const int q = tid + j * kBlock;
+            gqr[j] = 0;
+            if (q < nq) gqr[j] = S.gpos[q0 + q];
+        }
+    };
+    fetch(0);
+    for (int k = 0; k < S.nchunk; ++k) {
+        // the chunk's gather lists into LDS (beyond kGpReg * kBlock pointers:
+        // read here)
+        {
+            const int32_t *gp = S.gptr + (size_t)k * (nt + 1);
+            const int q0 = gp[0];
+#pragma unroll
+            for (int j = 0; j < kGpReg; ++j) {
+                const int t = tid + j * kBlock;
+                if (t <= nt) gpl[t] = gpr[j];
+            }
+            for (int t = tid + kGpReg * kBlock; t <= nt; t += kBlock) gpl[t] = gp[t] - q0;
+#pragma unroll
+            for (int j = 0; j < kGqReg; ++j) gpo[tid + j * kBlock] = gqr[j];
+        }
+#pragma unroll
+        for (int j = 0; j < kDetsPerThread; ++j) {
+            const DetDesc &D = Dc[j];
             const int s = D.s;
             if (s == 0) continue;
-            double *dst = cb + (S.adj_off[d] - base);
-            double coef = 0.0;
-            if (s <= dmax) {
-                const size_t o = rv_index(a, sp, d, w);
-                const double wt = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
-                coef = wt * (double)D.eps * pow2(delta_exponent(D, Ex, occ0) - K);
-            }
+            double *dst = cb + oc[j];
+            const double coef =
+                (s <= dmax) ? wc[j] * (double)D.eps * pow2(delta_exponent(D, Ex, occ0) - K) : 0.0;
             switch (s) {
             case 1: stage_adj<1>(D, T, M, coef, dst); break;
             case 2: stage_adj<2>(D, T, M, coef, dst); break;
@@ -941,6 +1035,7 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
             }
         }
         __syncthreads();
+        if (k + 1 < S.nchunk) fetch(k + 1);
         for (int t = tid; t < nt; t += kBlock) {
             double g = 0.0;
             for (int q = gpl[t]; q < gpl[t + 1]; ++q) g += cb[gpo[q]];
@@ -955,39 +1050,51 @@ __global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
         Y[idx] = s;
     }
     __syncthreads();
-    // Zc = T Y: nz segments of m per entry, partial sums in cb
-    const int nz = max(1, min(4, kBlock / (n * n)));
+    // Zc = T Y: nz segments of m per entry, partial sums in scr
+    const int nz = max(1, min(4, kDerivScratch / (n * n)));
     if (tid < nz * n * n) {
         const int idx = tid / nz, g = tid - idx * nz;
         const int c = idx / n, e = idx - c * n;
         double s = 0.0;
         for (int m = g; m < M; m += nz) s += T[c * M + m] * Y[m * n + e];
-        cb[tid] = s;
+        scr[tid] = s;
     }
     __syncthreads();
     for (int idx = tid; idx < n * n; idx += kBlock) {
         double s = 0.0;
-        for (int g = 0; g < nz; ++g) s += cb[idx * nz + g];
+        for (int g = 0; g < nz; ++g) s += scr[idx * nz + g];
         Zc[idx] = s;
     }
     __syncthreads();
-    // s1[e][q] = sum_m G_q[e][m] 2^-E[m] Y[m][e]: kFin segments of m per (e, q)
-    constexpr int kFin = 4;
+    // s1[e][q] = sum_m G_q[e][m] 2^-E[m] Y[m][e]: nf segments of m per (e, q),
+    // eight loads in flight per step
+    const int nf = max(1, min(8, kDerivScratch / (4 * n)));
     const double *phig = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
-    if (tid < kFin * 4 * n) {
-        const int pr = tid / kFin, g = tid - pr * kFin;
+    if (tid < nf * 4 * n) {
+        const int pr = tid / nf, g = tid - pr * nf;
         const int e = pr >> 2, q = pr & 3;
         const double *Gq = phig + (size_t)e * 5 * M + (size_t)(1 + q) * M;
         double s = 0.0;
-        for (int m = g; m < M; m += kFin) s += (Gq[m] * pow2(-Ex[m])) * Y[m * n + e];
-        cb[tid] = s;
+        int m = g;
+        for (; m + 7 * nf < M; m += 8 * nf) {
+            double gv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gv[u] = Gq[m + u * nf];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int mm = m + u * nf;
+                s += (gv[u] * pow2(-Ex[mm])) * Y[mm * n + e];
+            }
+        }
+        for (; m < M; m += nf) s += (Gq[m] * pow2(-Ex[m])) * Y[m * n + e];
+        scr[tid] = s;
     }
     __syncthreads();
     if (tid < 4 * n) {
         const int e = tid >> 2, q = tid & 3;
         const double *Gq = phig + (size_t)e * 5 * M + (size_t)(1 + q) * M;
         double s1 = 0.0, s2 = 0.0;
-        for (int g = 0; g < kFin; ++g) s1 += cb[tid * kFin + g];
+        for (int g = 0; g < nf; ++g) s1 += scr[tid * nf + g];
         for (int c = 0; c < n; ++c) s2 += (Gq[occ0[c]] * pow2(-Ex[occ0[c]])) * Zc[c * n + e];
         const size_t o = ((size_t)w * N + S.e0 + e) * 4 + q;
         a.gl_out[o] = a.wk.g0[o] + (s1 - s2) / psi_value(a, w);
@@ -1229,7 +1336,7 @@ __device__ void stage_orbitals(const KernelArgs &a, int w, int e0, int n, const 
 // pass 1: mantissa and exponent of every determinant of the flagged pairs,
 // and the integer maximum of the exponents per (walker, spin)
 template <int NT>
-__global__ void __launch_bounds__(kDirectBlock) k_direct_ratios_t(KernelArgs a) {
+__global__ void __launch_bounds__(kDirectBlock, 2) k_direct_ratios_t(KernelArgs a) {
     const int M = a.M, tid = threadIdx.x, split = a.direct_split;
     extern __shared__ double lds[];
     double *P0 = lds;                 // [NT][M] scaled orbital values of the pair's spin
@@ -1549,22 +1656,25 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     const int W = (int)a.W;
     const int n = a.nmax, M = a.M;
     const dim3 g2(2 * W), blk(kBlock);
-    auto mark = [&](int k) {
-        if (ev) (void)hipEventRecord(ev[k], st);
+    auto mark = [&](int k, bool end) {
+        if (ev) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], st);
     };
-    mark(0);
-    const size_t prim_bytes = (size_t)M * a.P * sizeof(Prim);
+    mark(0, false);
+    const size_t prim_bytes = (size_t)M * a.P * kPrimLdsBytes;
     const size_t lds_ref = sizeof(double) * (14 * (size_t)n * n + (size_t)a.N * (3 * kPowLd + 1)) +
                            sizeof(int) * 4 * (size_t)M + (prim_bytes <= kPrimLdsMax ? prim_bytes : 0);
     k_reference<<<dim3(W), blk, lds_ref, st>>>(a);
-    mark(1);
+    mark(0, true);
+    mark(1, false);
     const size_t lds_rat = sizeof(double) * ((size_t)n * M + n * n) + sizeof(int) * (M + n);
     k_ratios<<<g2, blk, lds_rat, st>>>(a);
-    mark(2);
+    mark(1, true);
+    mark(2, false);
     launch_direct_n(a, st, false);
     k_direct_scale<<<dim3((unsigned)std::min<int64_t>(2 * (int64_t)W * a.direct_split, 1024)),
                      blk, 0, st>>>(a);
-    mark(3);
+    mark(2, true);
+    mark(3, false);
     const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
     const dim3 gs((tiles + 7) / 8 * 8 * a.psi_nparts, 2), bs(64 * kSpmmWaves);
     if (a.precision == MDET_MIXED)
@@ -1575,15 +1685,18 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
         k_spmm<double, kSpmmCols64><<<gs, bs, 0, st>>>(
             a, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
             a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
-    mark(4);
-    const size_t lds_der = sizeof(double) * (3 * (size_t)n * M + 2 * n * n + kAdjChunk) +
-                           sizeof(int) * (M + n + (size_t)n * M + 1) + sizeof(uint16_t) * kAdjChunk;
+    mark(3, true);
+    mark(4, false);
+    const size_t lds_der = sizeof(double) * (2 * (size_t)n * M + n * n + deriv_union_doubles(n, M)) +
+                           sizeof(int) * (M + n);
     k_deriv<<<g2, blk, lds_der, st>>>(a);
-    mark(5);
+    mark(4, true);
+    mark(5, false);
     launch_direct_n(a, st, true);
-    mark(6);
+    mark(5, true);
+    mark(6, false);
     k_finalize<<<dim3((unsigned)(((int64_t)W * 4 * a.N + kBlock - 1) / kBlock)), blk, 0, st>>>(a);
-    mark(7);
+    mark(6, true);
     return hipGetLastError();
 }
 
