@@ -6,7 +6,11 @@ walkers), mixed precision and FP64, on one GPU.
 A step is one call of the whole hot path (orbitals, reference LU, table,
 ratios, sparse combination, derivatives) on a batch of 1024 walkers whose
 coordinates already sit in HBM; a pool of 8 walker batches is rotated so
-consecutive steps see different walkers.  Prints one JSON line.
+consecutive steps see different walkers.  The launch configuration is chosen
+by the library's autotuner during the warm-up.  `value` is the eager rate
+(kernels launched one by one, per-kernel HIP events on the stream);
+`graph_value` is the same steps replayed as captured HIP graphs.  Prints one
+JSON line.
 """
 import argparse
 import json
@@ -70,7 +74,9 @@ def kernel_model(name, wl, st, W, precision, n_fallback=0):
     return 0, 0, "fp64"
 
 
-def run_gpu(wl, precision, steps, warmup, pool):
+def run_gpu(wl, precision, steps, warmup, pool, tune=True):
+    """Eager timed region (per-kernel HIP events on the stream), then the same
+    steps replayed as captured HIP graphs (launch overhead removed)."""
     import torch
     import paper_1510_00730_amd as mdet
     ev = mdet.Evaluator(0)
@@ -82,6 +88,8 @@ def run_gpu(wl, precision, steps, warmup, pool):
            torch.empty((W, N, 4), dtype=torch.float64, device="cuda"),
            torch.empty(W, dtype=torch.int32, device="cuda"))
     stream = torch.cuda.current_stream()
+    if tune:  # the library's launch-configuration search (part of the warm-up)
+        ev.autotune(Rpool[0], precision=precision, n_rep=5)
     for k in range(warmup):
         ev.eval_walkers(Rpool[k % len(Rpool)], precision=precision, out=out, stream=stream)
     torch.cuda.synchronize()
@@ -95,23 +103,80 @@ def run_gpu(wl, precision, steps, warmup, pool):
     times, calls = ev.kernel_times()
     ev.set_profiling(False)
     ws = out[3].cpu().numpy()
+    # graph replay of the same steps (one capture per walker buffer, untimed)
+    for k in range(len(Rpool)):
+        ev.eval_graph(Rpool[k], precision=precision, out=out, stream=stream)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    for k in range(steps):
+        ev.eval_graph(Rpool[k % len(Rpool)], precision=precision, out=out, stream=stream)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
     st = ev.stats()
+    cfg = ev.launch_config()
     ev.close()
-    return (t1 - t0), times, calls, st, ws
+    return dict(dt=t1 - t0, dt_graph=g1 - g0, times=times, calls=calls, st=st, ws=ws, cfg=cfg)
 
 
-def cpu_baseline(wl, n_walk):
+def cpu_baseline(wl, seconds):
+    """The FP64 oracle on the host cores, on batches of the same walkers until
+    `seconds` of wall time have passed (at least one batch)."""
     import oracle
     cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
     cores = max(1, min(cores, os.cpu_count() or 1))
-    R = wl.R[:n_walk]
-    oracle.evaluate(wl, R[:cores], n_threads=cores)   # warm-up (page-in, thread pool)
+    batch = 128
+    oracle.evaluate(wl, wl.R[:cores], n_threads=cores)   # warm-up (page-in, thread pool)
+    done, k = 0, 0
     t0 = time.perf_counter()
-    oracle.evaluate(wl, R, n_threads=cores)
+    while True:
+        b0 = (k * batch) % wl.n_walk
+        oracle.evaluate(wl, wl.R[b0:b0 + batch], n_threads=cores)
+        done += min(batch, wl.n_walk - b0)
+        k += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
     dt = time.perf_counter() - t0
-    return {"value": n_walk / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_walk} walkers of the same workload, one evaluation each, FP64 oracle "
-                      f"(one LU per distinct determinant, Eq. (1) compensated sum), {dt:.1f} s wall"}
+    return {"value": done / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} walker evaluations ({k} batches of up to {batch} of the same "
+                      f"{wl.n_walk} walkers), FP64 oracle (one LU per distinct determinant, "
+                      f"Eq. (1) compensated sum), {dt:.1f} s wall"}
+
+
+def copy_probe(mib, reps):
+    """A plain device copy of known size (for scaling HBM traffic counters)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                      "reps": reps}), flush=True)
+
+
+def read_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.md")
+    src = os.path.join(ROOT, "paper_1510_00730_amd", "csrc", "mdet_kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for ln in text.splitlines():
+        if ":" in ln and ln.startswith("- "):
+            k, v = ln[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source sha256") != sha:
+        return None
+    try:
+        return float(vals["HBM bytes per launch (scaled)"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -121,24 +186,31 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--config", type=int, default=3)
-    ap.add_argument("--cpu-walkers", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB buffer (traffic-counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); walkers are independent, "
               "so more GPUs would each run this same per-GPU workload.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe, 5)
+        return
     from gen.workloads import make_config, walker_pool
     wl = make_config(args.config)
     pool = walker_pool(wl, 8)
     prec = 1 if args.precision == "mixed" else 0
     res = {}
     for p in (prec, 1 - prec):
-        dt, times, calls, st, ws = run_gpu(wl, p, args.steps, args.warmup, pool)
-        res[p] = dict(dt=dt, times=times, calls=calls, st=st, ws=ws)
-        print(f"[bench] precision {'mixed' if p else 'fp64'}: {args.steps * wl.n_walk / dt:.4g} "
-              f"walker-steps/s, {1e3 * dt / args.steps:.3f} ms/step, kernels (ms/launch): "
-              + ", ".join(f"{k} {v / max(calls, 1):.4f}" for k, v in times.items()),
+        r = run_gpu(wl, p, args.steps, args.warmup, pool, tune=not args.no_tune)
+        res[p] = r
+        print(f"[bench] precision {'mixed' if p else 'fp64'}: {args.steps * wl.n_walk / r['dt']:.4g} "
+              f"walker-steps/s eager, {args.steps * wl.n_walk / r['dt_graph']:.4g} graph, "
+              f"{1e3 * r['dt'] / args.steps:.3f} ms/step, config {r['cfg']}, kernels (ms/launch): "
+              + ", ".join(f"{k} {v / max(r['calls'], 1):.4f}" for k, v in r["times"].items()),
               file=sys.stderr, flush=True)
     r = res[prec]
     W = wl.n_walk
@@ -155,7 +227,7 @@ def main():
         roof = {"bound": "alu", "achieved": flops / t / 1e12, "peak": peak_f / 1e12,
                 "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = read_traffic(dom)
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
     roof["algorithmic_flops"] = flops
@@ -171,19 +243,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 sparse combination + f64" if prec == 1 else "f64",
+        "dtype": "f64+f32" if prec == 1 else "f64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: 9+8 electrons, 100 orbitals x 4 primitives, "
                                f"1000+1000 distinct dets, 1e5 products, {W} walkers",
                    "precision": args.precision, "walker_batch": W,
+                   "launch_config": list(r["cfg"]),
                    "fallback_fraction": float(np.mean(r["ws"] == 1))},
         "fp64_value": args.steps * W / res[0]["dt"],
         "mixed_value": args.steps * W / res[1]["dt"],
+        "graph_value": args.steps * W / r["dt_graph"],
         "kernel_ms_per_launch": {k: v / max(r["calls"], 1) for k, v in r["times"].items()},
         "roofline": roof,
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_walkers)
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
