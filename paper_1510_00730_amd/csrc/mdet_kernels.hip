@@ -382,54 +382,68 @@ __device__ __forceinline__ void wave_lds_sync() {
 // row i.  Rows are never exchanged: the pivot of column j is the unused lane
 // with the largest |entry| (lowest lane on ties), and the lane that pivots
 // column c ends up holding row c of A^-1 with column plane[j] in slot j.
-// The inverse is written to Xo (LDS, row-major); logabs and sign receive
-// ln|det A| and its sign.  Returns false on an exactly zero (or NaN) pivot.
-__device__ bool lane_gauss_jordan(int n, int lane, const double *A, double *Xo, double &logabs,
-                                  double &sign) {
+// The pivot search and the pivot row go through the wave's LDS scratch sc
+// (at least 2 kMaxN + 1 doubles).  The inverse is written to Xo (LDS,
+// row-major); logabs and sign receive ln|det A| and its sign.  Returns false
+// on an exactly zero, infinite or NaN pivot.
+__device__ bool lane_gauss_jordan(int n, int lane, const double *A, double *Xo, double *sc,
+                                  double &logabs, double &sign) {
     double r[kMaxN];
 #pragma unroll
     for (int k = 0; k < kMaxN; ++k) r[k] = (lane < n && k < n) ? A[lane * n + k] : 0.0;
+    double *cand = sc, *prow = sc + kMaxN;  // |candidates| per lane, normalised pivot row
     int pc = -1;
     int plane[kMaxN];
-    logabs = 0.0;
+    double mant = 1.0;
+    int ex = 0;
     sign = 1.0;
 #pragma unroll
     for (int j = 0; j < kMaxN; ++j) {
         if (j >= n) break;
-        double v = (pc < 0 && lane < n) ? fabs(r[j]) : -1.0;
-        if (v != v) v = INFINITY;  // NaN: pick it, the result is flagged anyway
-        int id = lane;
+        if (lane < kMaxN) {
+            double v = (pc < 0 && lane < n) ? fabs(r[j]) : -1.0;
+            if (v != v) v = INFINITY;  // NaN: pick it, then fail below
+            cand[lane] = v;
+        }
+        wave_lds_sync();
+        double best = cand[0];
+        int id = 0;
 #pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-            const double v2 = __shfl_xor(v, off, 16);
-            const int i2 = __shfl_xor(id, off, 16);
-            if (v2 > v || (v2 == v && i2 < id)) {
-                v = v2;
-                id = i2;
+        for (int l = 1; l < kMaxN; ++l) {
+            const double v = cand[l];
+            if (v > best) {
+                best = v;
+                id = l;
             }
         }
         id = __builtin_amdgcn_readfirstlane(id);
-        if (!(v > 0.0) || !(v < INFINITY)) return false;
+        if (!(best > 0.0) || !(best < INFINITY)) return false;
         plane[j] = id;
         const double f = r[j];
-        const double piv = __shfl(f, id, 16);
-        const double rinv = 1.0 / piv;
-        logabs += log(fabs(piv));
-        if (piv < 0.0) sign = -sign;
         if (lane == id) {
+            const double rinv = 1.0 / f;
             pc = j;
             r[j] = 1.0;
 #pragma unroll
-            for (int k = 0; k < kMaxN; ++k) r[k] *= rinv;
+            for (int k = 0; k < kMaxN; ++k) {
+                r[k] *= rinv;
+                if (k < n) prow[k] = r[k];
+            }
+            prow[kMaxN] = f;
         }
-        double pr[kMaxN];
-#pragma unroll
-        for (int k = 0; k < kMaxN; ++k) pr[k] = (k < n) ? __shfl(r[k], id, 16) : 0.0;
+        wave_lds_sync();
+        const double piv = prow[kMaxN];
+        mant *= piv;
+        int kk;
+        mant = frexp(mant, &kk);
+        ex += kk;
         if (lane != id) {
             r[j] = 0.0;
 #pragma unroll
-            for (int k = 0; k < kMaxN; ++k) r[k] -= f * pr[k];
+            for (int k = 0; k < kMaxN; ++k)
+                if (k < n) r[k] -= f * prow[k];
         }
+        wave_lds_sync();  // cand / prow are rewritten by the next step
     }
     // det A = det(Q) prod piv, Q the permutation j -> plane[j]
     int inv = 0;
@@ -438,7 +452,9 @@ __device__ bool lane_gauss_jordan(int n, int lane, const double *A, double *Xo, 
 #pragma unroll
         for (int j = i + 1; j < kMaxN; ++j)
             if (j < n && plane[i] > plane[j]) ++inv;
+    if (mant < 0.0) sign = -sign;
     if (inv & 1) sign = -sign;
+    logabs = log(fabs(mant)) + (double)ex * 0.69314718055994530942;
     if (pc >= 0) {
 #pragma unroll
         for (int j = 0; j < kMaxN; ++j)
@@ -457,7 +473,8 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
                                       // reference columns, Q[sp][q][e*n + c]
     double *Xl = Q + 10 * nn;         // [2][nm*nm]
     double *Rl = Xl + 2 * nn;         // [2][nm*nm]
-    int *emax = (int *)(Rl + 2 * nn); // [2][M] largest binary exponent of |phi| per column
+    double *gsc = Rl + 2 * nn;        // [2][2 kMaxN + 2] Gauss-Jordan scratch per wave
+    int *emax = (int *)(gsc + 2 * (2 * kMaxN + 2));  // [2][M] largest exponent of |phi| per column
     int *slot = emax + 2 * M;         // [2][M] reference slot of orbital m, or -1
     double *pw = (double *)(slot + 2 * M);  // [N][3][kPowLd] coordinate powers
     double *r2s = pw + N * 3 * kPowLd;      // [N] |r|^2
@@ -548,10 +565,7 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     double *X = Xl + sp * nn, *Rm = Rl + sp * nn;
     double la = 0.0, sg = 1.0;
     bool ok = true;
-    if (lane < 16) ok = lane_gauss_jordan(n, lane, A, X, la, sg);
-    ok = __shfl(ok ? 1 : 0, 0, 64) != 0;
-    la = __shfl(la, 0, 64);
-    sg = __shfl(sg, 0, 64);
+    ok = lane_gauss_jordan(n, lane, A, X, gsc + sp * (2 * kMaxN + 2), la, sg);
     if (lane == 0) a.wk.Kmax[ws] = INT_MIN;
     if (!ok) {
         if (lane == 0) {
@@ -568,12 +582,19 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         a.wk.sign0[ws] = sg;
     }
     wave_lds_sync();
-    // one residual-correction step: X <- X + X (I - A X)
-    for (int idx = lane; idx < n * n; idx += 64) {
-        const int i = idx / n, j = idx - i * n;
-        double t = (i == j) ? 1.0 : 0.0;
-        for (int k = 0; k < n; ++k) t -= A[i * n + k] * X[k * n + j];
-        Rm[idx] = t;
+    // one residual-correction step: X <- X + X (I - A X); the n-term dot
+    // products are unrolled so that their LDS reads are in flight together
+#pragma unroll
+    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
+        const int idx = lane + 64 * t;
+        if (idx < n * n) {
+            const int i = idx / n, j = idx - i * n;
+            double u = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < kMaxN; ++k)
+                if (k < n) u -= A[i * n + k] * X[k * n + j];
+            Rm[idx] = u;
+        }
     }
     wave_lds_sync();
     double xr[kMaxN * kMaxN / 64];
@@ -582,9 +603,11 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         const int idx = lane + 64 * t;
         if (idx < n * n) {
             const int i = idx / n, j = idx - i * n;
-            double s = X[idx];
-            for (int k = 0; k < n; ++k) s += X[i * n + k] * Rm[k * n + j];
-            xr[t] = s;
+            double u = X[idx];
+#pragma unroll
+            for (int k = 0; k < kMaxN; ++k)
+                if (k < n) u += X[i * n + k] * Rm[k * n + j];
+            xr[t] = u;
         }
     }
     wave_lds_sync();
@@ -600,11 +623,14 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     wave_lds_sync();
     // conditioning: kappa_1 = ||A||_1 ||X||_1 (largest column sums)
     double ca = 0.0, cx = 0.0;
-    if (lane < n)
-        for (int i = 0; i < n; ++i) {
-            ca += fabs(A[i * n + lane]);
-            cx += fabs(X[i * n + lane]);
-        }
+    if (lane < n) {
+#pragma unroll
+        for (int i = 0; i < kMaxN; ++i)
+            if (i < n) {
+                ca += fabs(A[i * n + lane]);
+                cx += fabs(X[i * n + lane]);
+            }
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         ca = fmax(ca, __shfl_xor(ca, off, 64));
@@ -616,7 +642,9 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         const int e = lane >> 2, q = lane & 3;
         const double *G = Q + (sp * 5 + 1 + q) * nn;
         double t = 0.0;
-        for (int c = 0; c < n; ++c) t += X[c * n + e] * G[e * n + c];
+#pragma unroll
+        for (int c = 0; c < kMaxN; ++c)
+            if (c < n) t += X[c * n + e] * G[e * n + c];
         a.wk.g0[((size_t)w * N + S.e0 + e) * 4 + q] = t;
     }
 }
@@ -1661,7 +1689,8 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     };
     mark(0, false);
     const size_t prim_bytes = (size_t)M * a.P * kPrimLdsBytes;
-    const size_t lds_ref = sizeof(double) * (14 * (size_t)n * n + (size_t)a.N * (3 * kPowLd + 1)) +
+    const size_t lds_ref = sizeof(double) * (14 * (size_t)n * n + 2 * (2 * kMaxN + 2) +
+                                             (size_t)a.N * (3 * kPowLd + 1)) +
                            sizeof(int) * 4 * (size_t)M + (prim_bytes <= kPrimLdsMax ? prim_bytes : 0);
     k_reference<<<dim3(W), blk, lds_ref, st>>>(a);
     mark(0, true);
