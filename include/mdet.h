@@ -106,7 +106,8 @@ mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim,
  * det_up, det_dn: uint64 [n_det][n_int] host; c: double [n_det] host.
  * Requires mdet_init_orbitals first.  Errors: MDET_ESPIN, MDET_EORBITAL,
  * MDET_EPOPCOUNT, MDET_EDUPLICATE, MDET_EDEGREE, MDET_EDIM (n_dn < 1,
- * n_up > MDET_MAX_SPIN_ELEC, n_up > n_mo, n_up * n_mo > 8192, or n_det
+ * n_up > MDET_MAX_SPIN_ELEC, n_up > n_mo, n_up * n_mo > 6144 (the per-walker tables
+ * of the derivative kernel must fit in LDS), or n_det
  * outside 1..2^30-1).
  * Synchronous.
  */

@@ -698,8 +698,8 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
         require(n_dn >= 1 && n_up <= MDET_MAX_SPIN_ELEC, MDET_EDIM, "electron count out of range");
         require(n_det <= (int64_t)INT32_MAX / 2, MDET_EDIM, "n_det too large");
         require(n_up <= ctx->n_mo, MDET_EDIM, "more electrons of one spin than orbitals");
-        require((int64_t)n_up * ctx->n_mo <= 8192, MDET_EDIM,
-                "n_up * n_mo above 8192 (per-walker tables must fit in LDS)");
+        require((int64_t)n_up * ctx->n_mo <= 6144, MDET_EDIM,
+                "n_up * n_mo above 6144 (per-walker tables must fit in LDS)");
         require(n_int == (ctx->n_mo + 63) / 64, MDET_EORBITAL, "n_int must equal ceil(n_mo/64)");
         for (int64_t k = 0; k < n_det; ++k)
             require(std::isfinite(c[k]), MDET_EINVAL, "non-finite coefficient");

@@ -121,3 +121,20 @@ def test_error_codes():
     ev.set_expansion(5, 5, wl.det_up, wl.det_dn, wl.c)                         # still usable
     _expect(-9, lambda: ev.eval_raw(1, None, 0, None, None, None, None, None, None))
     _expect(-1, lambda: ev.set_fallback_threshold(-1.0))
+
+
+def test_table_size_limit():
+    """n_up * n_mo above 6144 is refused (the derivative kernel's per-walker
+    tables must fit in LDS); 6144 itself is accepted."""
+    for n_mo, n_up, code in ((512, 13, -2), (512, 12, 0)):
+        rng = np.random.default_rng(5)
+        ev = mdet.Evaluator(device=-1)
+        ev.init_orbitals(np.zeros((n_mo, 1, 3), np.int32), np.ones((n_mo, 1)),
+                         rng.normal(size=(n_mo, 1)))
+        up = encode([list(range(n_up)), list(range(1, n_up + 1))], 8)
+        dn = encode([list(range(n_up)), list(range(n_up))], 8)
+        c = np.array([0.9, 0.1])
+        if code:
+            _expect(code, lambda: ev.set_expansion(n_up, n_up, up, dn, c, n_int=8))
+        else:
+            ev.set_expansion(n_up, n_up, up, dn, c, n_int=8)
