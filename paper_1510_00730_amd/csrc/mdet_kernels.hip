@@ -332,33 +332,100 @@ __device__ __forceinline__ double ratio_any(const DetDesc &D, const double *T, i
     }
 }
 
+// In-place Gauss-Jordan inversion with partial pivoting (row interchanges,
+// undone as column interchanges at the end) of a[S][S] in registers; det
+// receives the determinant.  Returns false on an exactly zero pivot.
+template <int S>
+__device__ __forceinline__ bool gj_inplace(double (&a)[S][S], double &det) {
+    int piv[S];
+    det = 1.0;
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        int p = j;
+        double best = fabs(a[j][j]);
+#pragma unroll
+        for (int i = j + 1; i < S; ++i)
+            if (fabs(a[i][j]) > best) {
+                best = fabs(a[i][j]);
+                p = i;
+            }
+        if (!(best > 0.0)) return false;
+        piv[j] = p;
+#pragma unroll
+        for (int i = j + 1; i < S; ++i)
+            if (i == p) {
+#pragma unroll
+                for (int k = 0; k < S; ++k) {
+                    const double t = a[i][k];
+                    a[i][k] = a[j][k];
+                    a[j][k] = t;
+                }
+                det = -det;
+            }
+        const double pv = a[j][j];
+        det *= pv;
+        const double r = 1.0 / pv;
+        a[j][j] = 1.0;
+#pragma unroll
+        for (int k = 0; k < S; ++k) a[j][k] *= r;
+#pragma unroll
+        for (int i = 0; i < S; ++i) {
+            if (i == j) continue;
+            const double f = a[i][j];
+            a[i][j] = 0.0;
+#pragma unroll
+            for (int k = 0; k < S; ++k) a[i][k] -= f * a[j][k];
+        }
+    }
+    // inverse of P A is A^-1 P^T: undo the row interchanges on the columns
+#pragma unroll
+    for (int j = S - 1; j >= 0; --j)
+#pragma unroll
+        for (int c = j + 1; c < S; ++c)
+            if (piv[j] == c) {
+#pragma unroll
+                for (int i = 0; i < S; ++i) {
+                    const double t = a[i][c];
+                    a[i][c] = a[i][j];
+                    a[i][j] = t;
+                }
+            }
+    return true;
+}
+
 // coef * C_ab of M_d into dst[a*S + b] (C_ab = adj[b][a]), compile-time s
 template <int S>
 __device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int M, double coef,
                                           double *dst) {
-    double m[S * S], adj[S * S];
-    load_exc<S>(D, T, M, m);
     if constexpr (S == 1) {
-        adj[0] = 1.0;
+        dst[0] = coef;
     } else if constexpr (S == 2) {
-        adj[0] = m[3];
-        adj[1] = -m[1];
-        adj[2] = -m[2];
-        adj[3] = m[0];
+        double m[4];
+        load_exc<2>(D, T, M, m);
+        dst[0] = coef * m[3];
+        dst[1] = -coef * m[2];
+        dst[2] = -coef * m[1];
+        dst[3] = coef * m[0];
     } else {
-        double det = 0.0;
-        if (gj_inverse<S>(m, adj, det)) {
+        double a[S][S];
 #pragma unroll
-            for (int t = 0; t < S * S; ++t) adj[t] *= det;
-        } else {
-            for (int a2 = 0; a2 < S; ++a2)  // exactly singular: explicit cofactors
-                for (int b2 = 0; b2 < S; ++b2) adj[b2 * S + a2] = cofactor(m, S, a2, b2);
+        for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int k = 0; k < S; ++k) a[i][k] = T[D.h[i] * M + D.p[k]];
+        double det = 0.0;
+        if (gj_inplace<S>(a, det)) {
+            const double cd = coef * det;  // adj = det * inverse; C_ab = adj[b][a]
+#pragma unroll
+            for (int i = 0; i < S; ++i)
+#pragma unroll
+                for (int k = 0; k < S; ++k) dst[i * S + k] = cd * a[k][i];
+        } else {  // exactly singular: explicit cofactors
+            double m[S * S];
+            load_exc<S>(D, T, M, m);
+            for (int a2 = 0; a2 < S; ++a2)
+                for (int b2 = 0; b2 < S; ++b2) dst[a2 * S + b2] = coef * cofactor(m, S, a2, b2);
         }
     }
-#pragma unroll
-    for (int a2 = 0; a2 < S; ++a2)
-#pragma unroll
-        for (int b2 = 0; b2 < S; ++b2) dst[a2 * S + b2] = coef * adj[b2 * S + a2];
 }
 
 }  // namespace
@@ -957,7 +1024,7 @@ __host__ __device__ inline size_t deriv_union_doubles(int n, int M) {
     return loop > tail ? loop : tail;
 }
 
-__global__ void __launch_bounds__(kBlock) k_deriv(KernelArgs a) {
+__global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
     const size_t ws = (size_t)w * 2 + sp;
     if (a.wk.flag[ws] != 0 || a.sp[sp].n == 0) return;
