@@ -133,12 +133,32 @@ mdet_status mdet_get_indexing(const mdet_ctx *ctx, int64_t *n_uniq_up, int64_t *
                               int64_t *ref_up, int64_t *ref_dn);
 
 /*
+ * Norm-based truncation of the expansion (Sec. 3, the improved truncation
+ * scheme): with N = sum_k c_k^2, the contribution of a distinct spin
+ * determinant is N_i^up = (sum of c_k^2 over the products holding it) / N
+ * (likewise N_j^dn); sum_i N_i^up = sum_j N_j^dn = 1.  Product k is kept iff
+ * N^up of its up determinant > eps_up and N^dn of its down determinant >
+ * eps_dn (a determinant at or below its threshold is removed with every
+ * product holding it).  Sums run over k in input order, in FP64.
+ * det_up, det_dn uint64 [n_det][n_int], c double [n_det], host, read only.
+ * Outputs (host, nullable): keep uint8 [n_det] (1 = kept); n_kept = kept
+ * products; n_up_kept, n_dn_kept = distinct spin determinants among them.
+ * No context needed.  Errors: MDET_EINVAL (null input, eps < 0 or NaN, all
+ * c zero), MDET_EDIM (n_int < 1 or n_det < 1).  Synchronous.
+ */
+mdet_status mdet_norm_truncation(int32_t n_int, int64_t n_det, const uint64_t *det_up,
+                                 const uint64_t *det_dn, const double *c, double eps_up,
+                                 double eps_dn, uint8_t *keep, int64_t *n_kept,
+                                 int64_t *n_up_kept, int64_t *n_dn_kept);
+
+/*
  * The hot path: for n_walk walkers, sign(Psi), ln|Psi| and grad~_e Psi / Psi
  * for every electron (the 4 x N array of Sec. 2.3).
  *  R_dev        double [n_walk][n_up+n_dn][3], device.
- *  precision    MDET_FP64: every step in FP64.  MDET_MIXED: the sparse
- *               combination over the n_det products (u = C R_dn, v = C^T R_up,
- *               psi) in FP32 with FP32 accumulation; LU, table, ratios and
+ *  precision    MDET_FP64: every step in FP64.  MDET_MIXED: the vectors of
+ *               the sparse combination over the n_det products (R_up, R_dn,
+ *               u = C R_dn, v = C^T R_up) are stored and moved in FP32, C and
+ *               every accumulation (u, v, psi) in FP64; LU, table, ratios and
  *               derivative aggregation stay FP64.
  *  max_degree_dev  int8 [n_walk] device or NULL: walker w keeps only products
  *               whose two spin determinants both have excitation degree

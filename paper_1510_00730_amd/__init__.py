@@ -4,7 +4,7 @@ The hot path lives in libmdet.so (HIP kernels for gfx950 behind the C ABI of
 include/mdet.h); this package is its Python binding.
 """
 from .binding import (MDET_FP64, MDET_MIXED, W_FALLBACK, W_NODE, W_OK, Evaluator,  # noqa: F401
-                      MdetError, load_library)
+                      MdetError, load_library, norm_truncation)
 
 __all__ = ["Evaluator", "MdetError", "MDET_FP64", "MDET_MIXED", "W_OK", "W_FALLBACK", "W_NODE",
-           "load_library"]
+           "load_library", "norm_truncation"]

@@ -30,7 +30,8 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_set_fallback_threshold", "mdet_get_stats", "mdet_set_profiling",
             "mdet_get_kernel_times", "mdet_rng_fill", "mdet_vmc_step", "mdet_mlp_forward",
             "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step", "mdet_set_launch_config",
-            "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune"]
+            "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune",
+            "mdet_norm_truncation"]
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
 RNG_UNIFORM, RNG_NORMAL = 0, 1
 
@@ -95,6 +96,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_get_launch_config": (I32, [P, P, P, P]),
         "mdet_eval_graph": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
         "mdet_autotune": (I32, [P, I64, P, I32, P, I32, P]),
+        "mdet_norm_truncation": (I32, [I32, I64, P, P, P, D, D, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -326,3 +328,25 @@ class Evaluator:
         self._check(_LIB.mdet_autotune(self._h, R.shape[0], _dptr(R), int(precision),
                                        _dptr(max_degree), int(n_rep), ctypes.byref(r)))
         return r
+
+
+def norm_truncation(det_up, det_dn, c, eps_up, eps_dn=None):
+    """Norm-based truncation (Sec. 3): keep mask [n_det] (bool) of the products
+    whose up and down determinants both contribute more than eps to the norm,
+    and the numbers of kept products and distinct up / down determinants."""
+    import numpy as np
+    du = np.ascontiguousarray(det_up, dtype=np.uint64)
+    dd = np.ascontiguousarray(det_dn, dtype=np.uint64)
+    cc = np.ascontiguousarray(c, dtype=np.float64)
+    if du.ndim == 1:
+        du = du[:, None]
+        dd = dd[:, None]
+    n_det, n_int = du.shape
+    keep = np.zeros(n_det, dtype=np.uint8)
+    nk, nu, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    rc = _LIB.mdet_norm_truncation(int(n_int), int(n_det), _ptr(du), _ptr(dd), _ptr(cc),
+                                   float(eps_up), float(eps_up if eps_dn is None else eps_dn),
+                                   _ptr(keep), ctypes.byref(nk), ctypes.byref(nu), ctypes.byref(nd))
+    if rc != 0:
+        raise MdetError(rc, "mdet_norm_truncation failed")
+    return keep.astype(bool), nk.value, nu.value, nd.value

@@ -860,6 +860,56 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
     });
 }
 
+mdet_status mdet_norm_truncation(int32_t n_int, int64_t n_det, const uint64_t *det_up,
+                                 const uint64_t *det_dn, const double *c, double eps_up,
+                                 double eps_dn, uint8_t *keep, int64_t *n_kept,
+                                 int64_t *n_up_kept, int64_t *n_dn_kept) {
+    try {
+        if (!det_up || !det_dn || !c) return MDET_EINVAL;
+        if (n_int < 1 || n_det < 1) return MDET_EDIM;
+        if (!(eps_up >= 0.0) || !(eps_dn >= 0.0)) return MDET_EINVAL;
+        SpinHost su, sd;
+        std::vector<int32_t> pu, pd;
+        unique_spin_list(det_up, n_det, n_int, su, pu);
+        unique_spin_list(det_dn, n_det, n_int, sd, pd);
+        double total = 0.0;
+        std::vector<double> nu(su.U, 0.0), nd(sd.U, 0.0);
+        for (int64_t k = 0; k < n_det; ++k) {  // input order
+            const double c2 = c[k] * c[k];
+            total += c2;
+            nu[pu[k]] += c2;
+            nd[pd[k]] += c2;
+        }
+        if (!(total > 0.0)) return MDET_EINVAL;
+        std::vector<uint8_t> ku(su.U, 0), kd(sd.U, 0), used_u(su.U, 0), used_d(sd.U, 0);
+        for (int64_t i = 0; i < su.U; ++i) ku[i] = nu[i] / total > eps_up;
+        for (int64_t j = 0; j < sd.U; ++j) kd[j] = nd[j] / total > eps_dn;
+        int64_t nk = 0, nuk = 0, ndk = 0;
+        for (int64_t k = 0; k < n_det; ++k) {
+            const uint8_t kk = ku[pu[k]] && kd[pd[k]];
+            if (keep) keep[k] = kk;
+            if (!kk) continue;
+            ++nk;
+            if (!used_u[pu[k]]) {
+                used_u[pu[k]] = 1;
+                ++nuk;
+            }
+            if (!used_d[pd[k]]) {
+                used_d[pd[k]] = 1;
+                ++ndk;
+            }
+        }
+        if (n_kept) *n_kept = nk;
+        if (n_up_kept) *n_up_kept = nuk;
+        if (n_dn_kept) *n_dn_kept = ndk;
+        return MDET_OK;
+    } catch (const std::bad_alloc &) {
+        return MDET_ENOMEM;
+    } catch (...) {
+        return MDET_EINVAL;
+    }
+}
+
 mdet_status mdet_get_indexing(const mdet_ctx *cctx, int64_t *n_uniq_up, int64_t *n_uniq_dn,
                               uint64_t *uniq_up, uint64_t *uniq_dn, int32_t *row_i, int32_t *col_j,
                               double *val, int64_t *src_pos, int64_t *ref_up, int64_t *ref_dn) {
