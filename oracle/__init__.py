@@ -7,6 +7,9 @@ shares no code with the GPU path.
 * ``oracle.c`` (built here with gcc into ``liboracle.so``): orbitals, one LU
   per distinct spin determinant, analytic derivative ratios, Eq. (1) and
   Eq. (main) sums.
+* ``sm_chain.c`` (same library): the paper's own method, Sherman-Morrison
+  substitutions along the sorted determinant list (Sec. 2.2), a CPU baseline
+  checked against the direct LU of ``oracle.c``.
 * ``preprocess.py``: the paper's determinant ordering and sparse indexing
   (Sec. 2.1), written independently of the library's C++ version.
 * ``brute.py``: brute-force references for tiny inputs.
@@ -22,16 +25,16 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "oracle.c")
+_SRC = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "sm_chain.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc (plain -O2, OpenMP, no fast-math)."""
+    """Compile oracle.c and sm_chain.c with gcc (plain -O2, OpenMP, no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", _SRC,
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", *_SRC,
                                "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -55,6 +58,10 @@ def _load():
         lib.orc_orbitals.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         lib.orc_slater.restype = ctypes.c_int
         lib.orc_slater.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+        I, L = ctypes.c_int, ctypes.c_int64
+        lib.orc_sm_eval.restype = ctypes.c_int
+        lib.orc_sm_eval.argtypes = [I, I, I, I, P, P, P, I, L, P, L, P, L, P, P, P, L, P,
+                                    ctypes.c_double, I, P, P, P, P]
         _lib = lib
     return _lib
 
@@ -126,3 +133,50 @@ def evaluate(wl, R=None, max_degree="auto", mode=0, n_threads=0, c=None,
     if rc != 0:
         raise ValueError(f"oracle rejected the input (code {rc})")
     return Result(sign, logabs, gl, rs_psi, rs_gl)
+
+
+class SMResult:
+    """sign [W], logabs [W], gl [W][N][4] and the chain counters summed over
+    walkers and both spins: n_subst (column substitutions done), n_inv
+    (factorisations from scratch), n_fail (postponed substitution attempts)."""
+
+    def __init__(self, sign, logabs, gl, stats, W):
+        self.sign, self.logabs, self.gl = sign, logabs, gl
+        self.n_subst, self.n_inv, self.n_fail = (int(x) for x in stats)
+        self.n_walk = W
+
+
+def sm_evaluate(wl, R=None, threshold=1e-3, n_threads=0, det_up=None, det_dn=None, c=None):
+    """Psi and grad~Psi/Psi by the paper's Sherman-Morrison chain (Sec. 2.2).
+
+    The distinct spin determinants are visited in the order of Eq. (comp)
+    (``preprocess.index_expansion``); every walker runs its own chain.  The
+    whole expansion is used (no per-walker excitation limit).
+    """
+    from . import preprocess
+    lib = _load()
+    R = wl.R if R is None else R
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    W, N = R.shape[0], wl.n_up + wl.n_dn
+    idx = preprocess.index_expansion(wl.det_up if det_up is None else det_up,
+                                     wl.det_dn if det_dn is None else det_dn,
+                                     wl.c if c is None else c)
+    uu = np.ascontiguousarray(idx["uniq_up"])
+    ud = np.ascontiguousarray(idx["uniq_dn"])
+    ri = np.ascontiguousarray(idx["row_i"], dtype=np.int32)
+    cj = np.ascontiguousarray(idx["col_j"], dtype=np.int32)
+    val = np.ascontiguousarray(idx["val"], dtype=np.float64)
+    pw = np.ascontiguousarray(wl.pow_abc, dtype=np.int32)
+    al = np.ascontiguousarray(wl.alpha, dtype=np.float64)
+    cf = np.ascontiguousarray(wl.coef, dtype=np.float64)
+    sign = np.zeros(W)
+    logabs = np.zeros(W)
+    gl = np.zeros((W, N, 4))
+    stats = np.zeros(3, dtype=np.int64)
+    rc = lib.orc_sm_eval(wl.n_up, wl.n_dn, wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf),
+                         uu.shape[1], uu.shape[0], _p(uu), ud.shape[0], _p(ud), val.shape[0],
+                         _p(ri), _p(cj), _p(val), W, _p(R), float(threshold), int(n_threads),
+                         _p(sign), _p(logabs), _p(gl), _p(stats))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (code {rc})")
+    return SMResult(sign, logabs, gl, stats, W)
