@@ -118,6 +118,69 @@ def run_gpu(wl, precision, steps, warmup, pool, tune=True):
     return dict(dt=t1 - t0, dt_graph=g1 - g0, times=times, calls=calls, st=st, ws=ws, cfg=cfg)
 
 
+def run_chain(wl, precision, steps, warmup, pool, chunks=(16, 32, 64, 128)):
+    """The paper's Sherman-Morrison chain (Sec. 2.2) on the same walkers: the
+    piece length is picked by a short sweep during the warm-up, then `steps`
+    eager steps are timed like the table method's."""
+    import torch
+    import paper_1510_00730_amd as mdet
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    W, N = wl.R.shape[0], wl.n_elec
+    Rpool = [torch.as_tensor(r, dtype=torch.float64, device="cuda") for r in pool]
+    out = (torch.empty(W, dtype=torch.float64, device="cuda"),
+           torch.empty(W, dtype=torch.float64, device="cuda"),
+           torch.empty((W, N, 4), dtype=torch.float64, device="cuda"),
+           torch.empty(W, dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream()
+    best, sweep = None, {}
+    for L in chunks:
+        ev.set_method(mdet.METHOD_SM_CHAIN, 1e-3, L)
+        for k in range(2):
+            ev.eval_walkers(Rpool[k], precision=precision, out=out, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(5):
+            ev.eval_walkers(Rpool[k % len(Rpool)], precision=precision, out=out, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        sweep[str(L)] = 1e3 * dt / 5
+        if best is None or dt < best[1]:
+            best = (L, dt)
+    L = best[0]
+    ev.set_method(mdet.METHOD_SM_CHAIN, 1e-3, L)
+    for k in range(warmup):
+        ev.eval_walkers(Rpool[k % len(Rpool)], precision=precision, out=out, stream=stream)
+    torch.cuda.synchronize()
+    ev.set_profiling(True)
+    counts = {"n_subst": 0, "n_inv": 0, "n_fail": 0, "n_start": 0}
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev.eval_walkers(Rpool[k % len(Rpool)], precision=precision, out=out, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    times, calls = ev.kernel_times()
+    ev.set_profiling(False)
+    for k in range(len(Rpool)):  # counters of one pass over the walker pool (untimed)
+        ev.eval_walkers(Rpool[k], precision=precision, out=out, stream=stream)
+        c = ev.sm_counters()
+        for key in counts:
+            counts[key] += c[key]
+    st = ev.stats()
+    ev.close()
+    nws = len(Rpool) * W
+    ndet = st.n_uniq_up + st.n_uniq_dn
+    return {"value": steps * W / (t1 - t0), "unit": "walker-steps/s",
+            "ms_per_step": 1e3 * (t1 - t0) / steps, "precision": "mixed" if precision else "fp64",
+            "threshold": 1e-3, "piece_length": L,
+            "piece_sweep_ms_per_step": sweep,
+            "per_walker_step": {k: v / nws for k, v in counts.items()},
+            "per_determinant": {"substitutions": counts["n_subst"] / (nws * ndet),
+                                "factorisations": (counts["n_inv"] + counts["n_start"]) / (nws * ndet),
+                                "retry_factorisations": counts["n_inv"] / (nws * ndet)},
+            "kernel_ms_per_launch": {k: v / max(calls, 1) for k, v in times.items() if v > 0}}
+
+
 def cpu_baseline(wl, seconds):
     """The FP64 oracle on the host cores, on batches of the same walkers until
     `seconds` of wall time have passed (at least one batch)."""
@@ -189,6 +252,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-chain", action="store_true",
+                    help="skip the Sherman-Morrison chain comparison run")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB buffer (traffic-counter calibration) and exit")
     args = ap.parse_args()
@@ -256,6 +321,12 @@ def main():
         "kernel_ms_per_launch": {k: v / max(r["calls"], 1) for k, v in r["times"].items()},
         "roofline": roof,
     }
+    if not args.no_chain:
+        ch = run_chain(wl, prec, min(args.steps, 50), min(args.warmup, 5), pool)
+        print(f"[bench] sm chain ({ch['precision']}, pieces of {ch['piece_length']}): "
+              f"{ch['value']:.4g} walker-steps/s, {ch['ms_per_step']:.3f} ms/step, "
+              f"{ch['per_walker_step']}", file=sys.stderr, flush=True)
+        line["sm_chain"] = ch
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(line), flush=True)

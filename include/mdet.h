@@ -185,6 +185,44 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
  */
 mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, double kappa_max);
 
+/* Evaluation methods of mdet_eval_walkers. */
+enum { MDET_METHOD_TABLE = 0, MDET_METHOD_SM_CHAIN = 1 };
+
+/*
+ * Select how the spin determinants are evaluated (Sec. 2.2 against Sec. 5).
+ *  MDET_METHOD_TABLE     (default) ratios from the table X Phi' of the
+ *                        reference, with the direct-LU fallback above.
+ *  MDET_METHOD_SM_CHAIN  the paper's chain: the distinct determinants in the
+ *                        sorted order of Eq. (comp), each reached from the
+ *                        previous one by Sherman-Morrison column substitutions
+ *                        (Eq. (sherman)) on its inverse.  A substitution whose
+ *                        determinant ratio has |r| < sm_threshold is postponed
+ *                        and retried after the others; a retry pass that
+ *                        completes none of the postponed ones restarts the
+ *                        determinant from an O(n^3) factorisation.  The list
+ *                        is cut into pieces of sm_chunk determinants that run
+ *                        in parallel, each started by a factorisation.
+ *                        grad~_e D / D comes from the current inverse
+ *                        (Sec. 2.3) and is stored per determinant
+ *                        (8 or 4 bytes x 4 n per determinant and walker,
+ *                        FP64 or mixed precision).  Walker status is always
+ *                        MDET_W_OK or MDET_W_NODE.
+ *  sm_threshold  > 0 (the paper uses 1e-3); ignored for the table method.
+ *  sm_chunk      >= 1 determinants per chain piece; ignored for the table.
+ * Returns MDET_EINVAL for an unknown method or out-of-range parameter.
+ */
+mdet_status mdet_set_method(mdet_ctx *ctx, int32_t method, double sm_threshold,
+                            int32_t sm_chunk);
+
+/*
+ * Counters of the last MDET_METHOD_SM_CHAIN evaluation on this context,
+ * summed over walkers and both spins: out[0] column substitutions done,
+ * out[1] factorisations forced by the retry rule or a singular predecessor,
+ * out[2] postponed substitution attempts, out[3] chain pieces started by a
+ * factorisation.  Synchronises the device.  Zeros if no chain evaluation ran.
+ */
+mdet_status mdet_get_sm_counters(mdet_ctx *ctx, int64_t *out4);
+
 typedef struct {
     int64_t n_det, n_uniq_up, n_uniq_dn;
     int32_t n_up, n_dn, n_mo, n_prim, n_int;

@@ -3,8 +3,9 @@
 The hot path lives in libmdet.so (HIP kernels for gfx950 behind the C ABI of
 include/mdet.h); this package is its Python binding.
 """
-from .binding import (MDET_FP64, MDET_MIXED, W_FALLBACK, W_NODE, W_OK, Evaluator,  # noqa: F401
-                      MdetError, load_library, norm_truncation)
+from .binding import (MDET_FP64, MDET_MIXED, METHOD_SM_CHAIN, METHOD_TABLE,  # noqa: F401
+                      W_FALLBACK, W_NODE, W_OK, Evaluator, MdetError, load_library,
+                      norm_truncation)
 
 __all__ = ["Evaluator", "MdetError", "MDET_FP64", "MDET_MIXED", "W_OK", "W_FALLBACK", "W_NODE",
-           "load_library", "norm_truncation"]
+           "METHOD_TABLE", "METHOD_SM_CHAIN", "load_library", "norm_truncation"]

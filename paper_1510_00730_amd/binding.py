@@ -31,7 +31,8 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_get_kernel_times", "mdet_rng_fill", "mdet_vmc_step", "mdet_mlp_forward",
             "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step", "mdet_set_launch_config",
             "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune",
-            "mdet_norm_truncation"]
+            "mdet_norm_truncation", "mdet_set_method", "mdet_get_sm_counters"]
+METHOD_TABLE, METHOD_SM_CHAIN = 0, 1
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
 RNG_UNIFORM, RNG_NORMAL = 0, 1
 
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_eval_graph": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
         "mdet_autotune": (I32, [P, I64, P, I32, P, I32, P]),
         "mdet_norm_truncation": (I32, [I32, I64, P, P, P, D, D, P, P, P, P]),
+        "mdet_set_method": (I32, [P, I32, D, I32]),
+        "mdet_get_sm_counters": (I32, [P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -171,6 +174,19 @@ class Evaluator:
 
     def set_fallback_threshold(self, kappa_max: float):
         self._check(_LIB.mdet_set_fallback_threshold(self._h, float(kappa_max)))
+
+    def set_method(self, method: int, sm_threshold: float = 1e-3, sm_chunk: int = 64):
+        """METHOD_TABLE (default) or METHOD_SM_CHAIN (Sec. 2.2 update chain)."""
+        self._check(_LIB.mdet_set_method(self._h, int(method), float(sm_threshold),
+                                         int(sm_chunk)))
+
+    def sm_counters(self):
+        """Chain counters of the last chain evaluation (synchronises):
+        dict(n_subst, n_inv, n_fail, n_start)."""
+        out = np.zeros(4, dtype=np.int64)
+        self._check(_LIB.mdet_get_sm_counters(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return dict(n_subst=int(out[0]), n_inv=int(out[1]), n_fail=int(out[2]),
+                    n_start=int(out[3]))
 
     def indexing(self):
         nu = ctypes.c_int64()

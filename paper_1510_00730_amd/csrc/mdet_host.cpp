@@ -5,10 +5,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <iterator>
 #include <new>
 #include <numeric>
 #include <stdexcept>
@@ -70,7 +72,20 @@ struct SpinHost {
     int64_t n_by_degree[MDET_MAX_DEGREE + 1] = {0};
     std::vector<int32_t> adj_off, chunk_det, gptr;
     std::vector<uint16_t> gpos;
+    // Sherman-Morrison chain lists (public order = chain order)
+    std::vector<int32_t> sm_exec, sm_off;
+    std::vector<uint16_t> sm_occ;
+    std::vector<uint32_t> sm_sub;
     DevBuf d_occ0, d_desc, d_adj_off, d_chunk_det, d_gptr, d_gpos;
+    DevBuf d_sm_exec, d_sm_occ, d_sm_off, d_sm_sub;
+    std::array<DevBuf *, 10> bufs() {
+        return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gptr, &d_gpos,
+                &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub};
+    }
+    std::array<const DevBuf *, 10> bufs() const {
+        return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gptr, &d_gpos,
+                &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub};
+    }
 };
 
 }  // namespace
@@ -96,6 +111,10 @@ struct mdet_ctx {
     DevBuf d_rseg32, d_cseg32, d_rdeg, d_cdeg;
     int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
     LaunchCfg cfg{0, 0, 1};
+    int32_t method = MDET_METHOD_TABLE;
+    double sm_threshold = 1e-3;
+    int32_t sm_chunk = 64;
+    bool sm_ran = false;  // a chain evaluation has been queued since the last reset
     hipStream_t own_stream = nullptr;
 
     // captured evaluations (mdet_eval_graph), keyed by every argument
@@ -122,15 +141,17 @@ struct mdet_ctx {
     static constexpr int kSetEvents = 2 * kNumKernels;
     bool profiling = false;
     std::vector<hipEvent_t> prof_ev;  // [kRing][kSetEvents]
+    uint32_t prof_mask[kRing] = {0};  // kernel slots recorded in each set
     int prof_head = 0, prof_pending = 0;
     double prof_ms[kNumKernels] = {0};
     int64_t prof_calls = 0;
     void harvest_one() {  // oldest pending set
         const int slot = (prof_head - prof_pending + kRing) % kRing;
         hipEvent_t *e = &prof_ev[(size_t)slot * kSetEvents];
-        (void)hipEventSynchronize(e[kSetEvents - 1]);  // the last kernel
         for (int k = 0; k < kNumKernels; ++k) {
+            if (!((prof_mask[slot] >> k) & 1u)) continue;
             float ms = 0.f;
+            (void)hipEventSynchronize(e[2 * k + 1]);
             if (hipEventElapsedTime(&ms, e[2 * k], e[2 * k + 1]) == hipSuccess) prof_ms[k] += ms;
         }
         ++prof_calls;
@@ -139,8 +160,9 @@ struct mdet_ctx {
     void harvest_all() {
         while (prof_pending > 0) harvest_one();
     }
-    hipEvent_t *next_event_set() {
+    hipEvent_t *next_event_set(uint32_t mask) {
         if (prof_pending == kRing) harvest_one();
+        prof_mask[prof_head] = mask;
         hipEvent_t *e = &prof_ev[(size_t)prof_head * kSetEvents];
         prof_head = (prof_head + 1) % kRing;
         ++prof_pending;
@@ -157,7 +179,8 @@ struct mdet_ctx {
     int64_t wcap = 0;
     DevBuf w_phi, w_E, w_X, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
         w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart, w_dcount, w_dlist, w_perm, w_Rs, w_mds, w_sign_s, w_logabs_s, w_gl_s,
-        w_ws_s;
+        w_ws_s, w_smstat;
+    DevBuf w_smg;  // chain method: per-determinant derivative ratios (grown on demand)
     Work wk{};
     // VMC / MLP work buffers (grow-only)
     int64_t vcap = 0;
@@ -178,12 +201,7 @@ struct mdet_ctx {
     void drop_expansion() {
         have_exp = false;
         for (auto &s : sp) {
-            s.d_occ0.release();
-            s.d_desc.release();
-            s.d_adj_off.release();
-            s.d_chunk_det.release();
-            s.d_gptr.release();
-            s.d_gpos.release();
+            for (DevBuf *b : s.bufs()) b->release();
             s = SpinHost();
         }
         drop_vmc();
@@ -195,8 +213,10 @@ struct mdet_ctx {
     void drop_work() {
         for (DevBuf *b : {&w_phi, &w_E, &w_X, &w_g0, &w_logdet0, &w_sign0, &w_flag, &w_K,
                           &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp, &w_Kmax, &w_dpart, &w_dcount, &w_dlist,
-                          &w_perm, &w_Rs, &w_mds, &w_sign_s, &w_logabs_s, &w_gl_s, &w_ws_s})
+                          &w_perm, &w_Rs, &w_mds, &w_sign_s, &w_logabs_s, &w_gl_s, &w_ws_s, &w_smstat,
+                          &w_smg})
             b->release();
+        sm_ran = false;
         wcap = 0;
         drop_graphs();
     }
@@ -205,7 +225,7 @@ struct mdet_ctx {
         for (const DevBuf *b : {&w_phi, &w_E, &w_X, &w_g0, &w_logdet0, &w_sign0, &w_flag,
                                 &w_K, &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp,
                                 &w_Kmax, &w_dpart, &w_dcount, &w_dlist, &w_perm, &w_Rs, &w_mds, &w_sign_s,
-                                &w_logabs_s, &w_gl_s, &w_ws_s})
+                                &w_logabs_s, &w_gl_s, &w_ws_s, &w_smstat, &w_smg})
             t += (int64_t)b->bytes;
         return t;
     }
@@ -215,8 +235,7 @@ struct mdet_ctx {
                                 &d_cval, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             t += (int64_t)b->bytes;
         for (const auto &s : sp)
-            t += (int64_t)(s.d_occ0.bytes + s.d_desc.bytes + s.d_adj_off.bytes +
-                           s.d_chunk_det.bytes + s.d_gptr.bytes + s.d_gpos.bytes);
+            for (const DevBuf *b : s.bufs()) t += (int64_t)b->bytes;
         return t;
     }
 };
@@ -392,6 +411,33 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
     }
 }
 
+// Lists of the Sherman-Morrison chain (Sec. 2.2): the public (sorted) order
+// is the chain order; between consecutive determinants the orbitals that
+// leave (ascending) are paired with those that enter (ascending).
+void chain_lists(SpinHost &s, int n_int) {
+    const int n = s.n;
+    s.sm_exec = s.exec_of;
+    s.sm_occ.assign((size_t)s.U * n, 0);
+    s.sm_off.assign(s.U + 1, 0);
+    s.sm_sub.clear();
+    std::vector<int32_t> prev;
+    for (int64_t i = 0; i < s.U; ++i) {
+        const std::vector<int32_t> occ = occupied(s.uniq.data() + i * n_int, n_int);
+        for (int c = 0; c < n; ++c) s.sm_occ[(size_t)i * n + c] = (uint16_t)occ[c];
+        if (i > 0) {
+            std::vector<int32_t> holes, parts;
+            std::set_difference(prev.begin(), prev.end(), occ.begin(), occ.end(),
+                                std::back_inserter(holes));
+            std::set_difference(occ.begin(), occ.end(), prev.begin(), prev.end(),
+                                std::back_inserter(parts));
+            for (size_t t = 0; t < holes.size(); ++t)
+                s.sm_sub.push_back((uint32_t)holes[t] | ((uint32_t)parts[t] << 16));
+        }
+        s.sm_off[i + 1] = (int32_t)s.sm_sub.size();
+        prev = occ;
+    }
+}
+
 // Segments of the CSR rows (CSC columns) by chunks of kSpmmCols gathered entries.
 std::vector<int32_t> chunk_segments(const std::vector<int32_t> &ptr, const std::vector<int32_t> &idx,
                                     int64_t rows, int64_t cols, int32_t width, int32_t &nch) {
@@ -464,6 +510,7 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     c->w_logabs_s.alloc(sizeof(double) * W);
     c->w_gl_s.alloc(sizeof(double) * W * N * 4);
     c->w_ws_s.alloc(sizeof(int32_t) * W);
+    c->w_smstat.alloc(sizeof(unsigned long long) * 4);
     Work &k = c->wk;
     k.W = W;
     k.Wld = Wld;
@@ -497,7 +544,25 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     k.logabs_s = c->w_logabs_s.as<double>();
     k.gl_s = c->w_gl_s.as<double>();
     k.ws_s = c->w_ws_s.as<int32_t>();
+    k.Umax = (int32_t)std::max(c->sp[0].U, c->sp[1].U);
+    k.smstat = c->w_smstat.as<unsigned long long>();
+    k.smg64 = nullptr;
+    k.smg32 = nullptr;
     c->wcap = W;
+}
+
+// Chain method: per-determinant derivative ratios for W walkers, allocated
+// before any capture (a reallocation drops the captured graphs).
+void ensure_chain(mdet_ctx *c, int64_t W) {
+    if (c->method != MDET_METHOD_SM_CHAIN) return;
+    const size_t need = sizeof(double) * (size_t)W * 2 * (size_t)c->wk.Umax * 4 *
+                        (size_t)std::max(1, c->wk.nmax);
+    if (c->w_smg.bytes < need) {
+        c->drop_graphs();
+        c->w_smg.alloc(need);
+    }
+    c->wk.smg64 = c->w_smg.as<double>();
+    c->wk.smg32 = c->w_smg.as<float>();
 }
 
 // Queue one evaluation (all kernels) on `st`; arguments already validated.
@@ -505,6 +570,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
                   const int8_t *max_degree_dev, double *sign_dev, double *logabs_dev,
                   double *gl_dev, int32_t *wstatus_dev, hipStream_t st) {
     ensure_work(ctx, n_walk);
+    ensure_chain(ctx, n_walk);
     KernelArgs a{};
     a.n_up = ctx->n_up;
     a.n_dn = ctx->n_dn;
@@ -533,6 +599,10 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
         d.chunk_det = ctx->sp[s].d_chunk_det.as<int32_t>();
         d.gptr = ctx->sp[s].d_gptr.as<int32_t>();
         d.gpos = ctx->sp[s].d_gpos.as<uint16_t>();
+        d.sm_exec = ctx->sp[s].d_sm_exec.as<int32_t>();
+        d.sm_occ = ctx->sp[s].d_sm_occ.as<uint16_t>();
+        d.sm_off = ctx->sp[s].d_sm_off.as<int32_t>();
+        d.sm_sub = ctx->sp[s].d_sm_sub.as<uint32_t>();
     }
     a.C.U = (int32_t)ctx->sp[0].U;
     a.C.V = (int32_t)ctx->sp[1].U;
@@ -554,6 +624,10 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.C.rdeg = ctx->d_rdeg.as<int32_t>();
     a.C.cdeg = ctx->d_cdeg.as<int32_t>();
     a.cfg = ctx->cfg;
+    a.method = ctx->method;
+    a.sm_threshold = ctx->sm_threshold;
+    a.sm_chunk = ctx->sm_chunk;
+    if (a.method == MDET_METHOD_SM_CHAIN) ctx->sm_ran = true;
     a.wk = ctx->wk;
     a.W = n_walk;
     a.R = R_dev;
@@ -563,7 +637,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.logabs_out = logabs_dev;
     a.gl_out = gl_dev;
     a.wstatus = wstatus_dev;
-    hipEvent_t *ev = ctx->profiling ? ctx->next_event_set() : nullptr;
+    hipEvent_t *ev = ctx->profiling ? ctx->next_event_set(kernels_of_method(a.method)) : nullptr;
     HIP_OK(launch_eval(a, st, ev));
 }
 
@@ -734,6 +808,8 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
         sp[1].ref = pos_d[kref];
         analyse_spin(sp[0], n_int, ctx->n_mo);
         analyse_spin(sp[1], n_int, ctx->n_mo);
+        chain_lists(sp[0], n_int);
+        chain_lists(sp[1], n_int);
 
         std::vector<int32_t> row_i(n_det), col_j(n_det);
         std::vector<double> val(n_det);
@@ -806,6 +882,10 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             sp[s].d_chunk_det.upload(sp[s].chunk_det);
             sp[s].d_gptr.upload(sp[s].gptr);
             sp[s].d_gpos.upload(sp[s].gpos);
+            sp[s].d_sm_exec.upload(sp[s].sm_exec);
+            sp[s].d_sm_occ.upload(sp[s].sm_occ);
+            sp[s].d_sm_off.upload(sp[s].sm_off);
+            sp[s].d_sm_sub.upload(sp[s].sm_sub);
         }
         if (!ctx->host_only) {
             ctx->d_rptr.upload(rptr);
@@ -845,6 +925,14 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             std::swap(ctx->sp[s].d_chunk_det, sp[s].d_chunk_det);
             std::swap(ctx->sp[s].d_gptr, sp[s].d_gptr);
             std::swap(ctx->sp[s].d_gpos, sp[s].d_gpos);
+            ctx->sp[s].sm_exec.swap(sp[s].sm_exec);
+            ctx->sp[s].sm_occ.swap(sp[s].sm_occ);
+            ctx->sp[s].sm_off.swap(sp[s].sm_off);
+            ctx->sp[s].sm_sub.swap(sp[s].sm_sub);
+            std::swap(ctx->sp[s].d_sm_exec, sp[s].d_sm_exec);
+            std::swap(ctx->sp[s].d_sm_occ, sp[s].d_sm_occ);
+            std::swap(ctx->sp[s].d_sm_off, sp[s].d_sm_off);
+            std::swap(ctx->sp[s].d_sm_sub, sp[s].d_sm_sub);
         }
         ctx->row_i.swap(row_i);
         ctx->col_j.swap(col_j);
@@ -977,6 +1065,36 @@ mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, double kappa_max) {
     return guarded(ctx, [&] {
         require(kappa_max > 0.0, MDET_EINVAL, "threshold must be positive");
         ctx->kappa_max = kappa_max;
+    });
+}
+
+mdet_status mdet_set_method(mdet_ctx *ctx, int32_t method, double sm_threshold,
+                            int32_t sm_chunk) {
+    return guarded(ctx, [&] {
+        require(method == MDET_METHOD_TABLE || method == MDET_METHOD_SM_CHAIN, MDET_EINVAL,
+                "unknown method");
+        if (method == MDET_METHOD_SM_CHAIN) {
+            require(sm_threshold > 0.0 && std::isfinite(sm_threshold), MDET_EINVAL,
+                    "sm_threshold must be positive and finite");
+            require(sm_chunk >= 1, MDET_EINVAL, "sm_chunk must be >= 1");
+            ctx->sm_threshold = sm_threshold;
+            ctx->sm_chunk = sm_chunk;
+        }
+        ctx->method = method;
+        ctx->drop_graphs();
+    });
+}
+
+mdet_status mdet_get_sm_counters(mdet_ctx *ctx, int64_t *out4) {
+    return guarded(ctx, [&] {
+        require(out4 != nullptr, MDET_EINVAL, "null output");
+        for (int k = 0; k < 4; ++k) out4[k] = 0;
+        if (ctx->host_only || !ctx->sm_ran || ctx->w_smstat.p == nullptr) return;
+        HIP_OK(hipSetDevice(ctx->device));
+        HIP_OK(hipDeviceSynchronize());
+        unsigned long long h[4];
+        HIP_OK(hipMemcpy(h, ctx->w_smstat.p, sizeof(h), hipMemcpyDeviceToHost));
+        for (int k = 0; k < 4; ++k) out4[k] = (int64_t)h[k];
     });
 }
 
@@ -1216,6 +1334,7 @@ mdet_status mdet_eval_graph(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, 
             st = ctx->own_stream;
         }
         ensure_work(ctx, n_walk);  // any allocation happens before capture
+        ensure_chain(ctx, n_walk);
         const void *key[7] = {R_dev, max_degree_dev, sign_dev, logabs_dev, gl_dev, wstatus_dev, nullptr};
         mdet_ctx::GraphEntry *hit = nullptr;
         for (auto &g : ctx->graphs)

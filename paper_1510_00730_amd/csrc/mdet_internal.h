@@ -59,6 +59,13 @@ struct SpinDev {
     const int32_t *chunk_det;  // [nchunk+1] determinant range of each chunk
     const int32_t *gptr;       // [nchunk][n*M+1] per-chunk gather lists, target t = c*M + m
     const uint16_t *gpos;      // adjugate slot (chunk-local) of each list entry
+    // Sherman-Morrison chain (Sec. 2.2): the distinct determinants in the
+    // sorted order of Eq. (comp), position i -> execution index sm_exec[i]
+    const int32_t *sm_exec;    // [U]
+    const uint16_t *sm_occ;    // [U][n] occupied orbitals, ascending
+    const int32_t *sm_off;     // [U+1] substitutions from position i-1 to i:
+    const uint32_t *sm_sub;    //   sm_sub[sm_off[i] .. sm_off[i+1]), hole | particle << 16,
+                               //   holes ascending paired with particles ascending
 };
 
 // Device view of the sparse coefficient matrix in execution indices.  The
@@ -112,6 +119,11 @@ struct Work {
     int8_t *mds;       // [W] maximum degrees in sorted order
     double *sign_s, *logabs_s, *gl_s;  // sorted-order outputs
     int32_t *ws_s;
+    // Sherman-Morrison chain method
+    int32_t Umax;      // max(U, V): determinant stride of the ratio derivatives
+    double *smg64;     // [W][2][Umax][4 nmax] grad~_e D / D per determinant (FP64 runs)
+    float *smg32;      // same storage, FP32 (mixed-precision runs)
+    unsigned long long *smstat;  // [4] substitutions, recomputations, rejected attempts, chunk starts
 };
 
 // Largest number of blocks per (walker, spin) of the direct-LU fallback.
@@ -143,13 +155,18 @@ struct KernelArgs {
     int32_t direct_split;     // determinant slices per listed pair of the direct-LU fallback
     int32_t direct_stage_grad;  // fallback stages orbital derivatives in LDS (else reads HBM)
     LaunchCfg cfg;
+    int32_t method;           // MDET_METHOD_TABLE or MDET_METHOD_SM_CHAIN
+    double sm_threshold;      // chain: smallest accepted |ratio| of one substitution
+    int32_t sm_chunk;         // chain: determinants per independently started chain piece
     double *sign_out, *logabs_out, *gl_out;
     int32_t *wstatus;
 };
 
 // Number of kernels of one evaluation (for per-kernel timing).
-constexpr int kNumKernels = 7;
+constexpr int kNumKernels = 9;
 const char *kernel_name(int k);
+// Bit k set: kernel slot k runs (and has its events recorded) in `method`.
+uint32_t kernels_of_method(int method);
 
 // Launch the whole evaluation on `stream`; returns hipSuccess or the first
 // error.  If `events` is not null, events[2k] and events[2k + 1] are recorded
