@@ -170,6 +170,21 @@ def run_chain(wl, precision, steps, warmup, pool, chunks=(16, 32, 64, 128)):
     ev.close()
     nws = len(Rpool) * W
     ndet = st.n_uniq_up + st.n_uniq_dn
+    # algorithmic FP64 work of k_sm_chain per walker-step from the measured
+    # counts: a substitution is a mat-vec and a rank-1 update (4 n^2 flops), a
+    # factorisation 2 n^3, the derivative ratios of a determinant 8 n^2 (n^2
+    # weighted over the two spin lists)
+    n2 = (wl.n_up ** 2 * st.n_uniq_up + wl.n_dn ** 2 * st.n_uniq_dn) / ndet
+    n3 = (wl.n_up ** 3 * st.n_uniq_up + wl.n_dn ** 3 * st.n_uniq_dn) / ndet
+    per = {k: v / nws for k, v in counts.items()}
+    flops = W * (4 * n2 * per["n_subst"] + 2 * n3 * (per["n_inv"] + per["n_start"]) + 8 * n2 * ndet)
+    t_k = times.get("k_sm_chain", 0.0) / max(calls, 1) * 1e-3
+    roof = None
+    if t_k > 0:
+        roof = {"bound": "alu", "kernel": "k_sm_chain", "achieved": flops / t_k / 1e12,
+                "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s", "avg_launch_ms": t_k * 1e3,
+                "algorithmic_flops": flops}
+        roof["frac"] = roof["achieved"] / roof["peak"]
     return {"value": steps * W / (t1 - t0), "unit": "walker-steps/s",
             "ms_per_step": 1e3 * (t1 - t0) / steps, "precision": "mixed" if precision else "fp64",
             "threshold": 1e-3, "piece_length": L,
@@ -178,7 +193,31 @@ def run_chain(wl, precision, steps, warmup, pool, chunks=(16, 32, 64, 128)):
             "per_determinant": {"substitutions": counts["n_subst"] / (nws * ndet),
                                 "factorisations": (counts["n_inv"] + counts["n_start"]) / (nws * ndet),
                                 "retry_factorisations": counts["n_inv"] / (nws * ndet)},
-            "kernel_ms_per_launch": {k: v / max(calls, 1) for k, v in times.items() if v > 0}}
+            "kernel_ms_per_launch": {k: v / max(calls, 1) for k, v in times.items() if v > 0},
+            "roofline": roof}
+
+
+def cpu_chain_baseline(wl, seconds):
+    """The paper's chain on the host cores (the oracle's CPU version), timed
+    on batches of the same walkers for about `seconds`."""
+    import oracle
+    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    cores = max(1, min(cores, os.cpu_count() or 1))
+    batch = 64
+    oracle.sm_evaluate(wl, wl.R[:cores], n_threads=cores)
+    done, k = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        b0 = (k * batch) % wl.n_walk
+        oracle.sm_evaluate(wl, wl.R[b0:b0 + batch], n_threads=cores)
+        done += min(batch, wl.n_walk - b0)
+        k += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} walker evaluations by the CPU Sherman-Morrison chain "
+                      f"(threshold 1e-3, one chain per walker and spin), {dt:.1f} s wall"}
 
 
 def cpu_baseline(wl, seconds):
@@ -218,15 +257,23 @@ def copy_probe(mib, reps):
                       "reps": reps}), flush=True)
 
 
+def kernel_source_sha():
+    """sha256 over the sources of the table-method kernels (the kernel file and
+    the device helpers it includes), as recorded in the counter summaries."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mdet_kernels.hip", "mdet_device.h"):
+        h.update(open(os.path.join(ROOT, "paper_1510_00730_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def read_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
     None when the kernel source changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.md")
-    src = os.path.join(ROOT, "paper_1510_00730_amd", "csrc", "mdet_kernels.hip")
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha()
     except OSError:
         return None
     vals = {}
@@ -326,6 +373,8 @@ def main():
         print(f"[bench] sm chain ({ch['precision']}, pieces of {ch['piece_length']}): "
               f"{ch['value']:.4g} walker-steps/s, {ch['ms_per_step']:.3f} ms/step, "
               f"{ch['per_walker_step']}", file=sys.stderr, flush=True)
+        if not args.no_cpu:
+            ch["cpu_baseline"] = cpu_chain_baseline(wl, min(args.cpu_seconds, 6.0))
         line["sm_chain"] = ch
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

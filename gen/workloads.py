@@ -206,6 +206,22 @@ def make_custom(n_up, n_dn, n_mo, n_prim, n_uniq_up, n_uniq_dn, degrees, n_det,
                     c=c, R=R, max_degree=md)
 
 
+def make_helium(n_walk: int, seed: int = 0, sigma: float = 0.8) -> Workload:
+    """Two electrons (one per spin) in one nodeless s orbital, a sum of two
+    Gaussians, as a single determinant: the helium atom (nuclear charge 2)
+    for the diffusion Monte Carlo checks.  Walkers start normal around the
+    nucleus."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    pow_abc = np.zeros((1, 2, 3), dtype=np.int32)
+    alpha = np.array([[0.45, 2.2]])
+    coef = np.array([[1.0, 0.6]])
+    det = encode([[0]], 1)
+    R = rng.normal(0.0, sigma, size=(n_walk, 2, 3))
+    return Workload(name="helium", n_up=1, n_dn=1, n_mo=1, n_prim=2, pow_abc=pow_abc,
+                    alpha=alpha, coef=coef, n_int=1, det_up=det.copy(), det_dn=det.copy(),
+                    c=np.array([1.0]), R=R, max_degree=None)
+
+
 def walker_pool(wl: Workload, n_pool: int, seed: int = 7, sigma: float = 2.0) -> np.ndarray:
     """Extra walker sets of the same distribution (rotated per timed step)."""
     rng = np.random.default_rng(np.random.SeedSequence(seed))

@@ -263,6 +263,50 @@ enum { MDET_PROP_GAUSSIAN = 0, MDET_PROP_DRIFT = 1, MDET_PROP_MLP = 2 };
 enum { MDET_RNG_UNIFORM = 0, MDET_RNG_NORMAL = 1 };
 
 /*
+ * Slater-Jastrow trial function.  The paper treats the Jastrow prefactor by
+ * standard O(N^2) techniques and leaves it out of its algorithm (Sec. 1);
+ * here it multiplies the expansion: Psi_T = exp(J) Psi with
+ *   J = sum_{i<j} a_ij r_ij / (1 + b_ee r_ij) + sum_i a_en r_i / (1 + b_en r_i),
+ * a_ij = 1/2 for electrons of opposite spin, 1/4 for equal spin (the
+ * electron-electron cusp conditions); a_en = -Z gives the cusp at a nucleus
+ * of charge Z at the origin, a_en = 0 drops the term.  When enabled, every
+ * evaluation (mdet_eval_walkers, mdet_eval_graph, the VMC and DMC steps)
+ * returns ln|Psi_T|, grad ln Psi_T and lap Psi_T / Psi_T instead of the
+ * expansion's values; the sign is unchanged.  Exactly coincident electrons
+ * give non-finite Laplacians.  b_ee, b_en >= 0 and finite.
+ */
+mdet_status mdet_set_jastrow(mdet_ctx *ctx, int32_t enable, double b_ee, double a_en,
+                             double b_en);
+
+/*
+ * One fixed-node diffusion Monte Carlo step for n_walk walkers (all device
+ * pointers, updated in place; the walker state is consistent on entry and
+ * on exit):
+ *  1. drift-diffusion move R' = R + tau grad ln|Psi(R)| + sqrt(tau) xi
+ *     (noise_dev [W][N][3] standard normals) with the Metropolis-Hastings
+ *     test of mdet_vmc_step (uniform_dev [W]); a move onto a node or across
+ *     one (sign of Psi changes) is rejected;
+ *  2. branching weight w <- w exp(-tau ((E_L(R) + E_L(R_new)) / 2 - e_trial)),
+ *     0 for a walker whose local energy is not finite; elocal_dev [W] holds
+ *     E_L at the walker's position on entry and is updated;
+ *  3. sums_dev [4] (device) receives, before the population is redrawn,
+ *     sum w, sum w E_L, sum w^2 and the number of accepted moves;
+ *  4. the population is redrawn at fixed size by the comb: new walker j is
+ *     a copy of the first walker i whose cumulative weight exceeds
+ *     (j + comb_u) sum w / n_walk (comb_u in [0, 1)); every copy carries
+ *     weight 1 in weight_dev [W].  If every weight is zero nothing is
+ *     redrawn.
+ * Z = nuclear_charge (point nucleus at the origin, as mdet_vmc_step).
+ * Deterministic for given random numbers.  Asynchronous on hip_stream.
+ */
+mdet_status mdet_dmc_step(mdet_ctx *ctx, int64_t n_walk, double tau, double e_trial,
+                          double nuclear_charge, int32_t precision, double *R_dev,
+                          double *sign_dev, double *logabs_dev, double *gl_dev, double *elocal_dev,
+                          double *weight_dev, const double *noise_dev, const double *uniform_dev,
+                          double comb_u, double *sums_dev, int32_t *accepted_dev,
+                          void *hip_stream);
+
+/*
  * Philox-4x32-10 counter-based random numbers (Salmon et al., SC'11).
  * Element pair i is drawn from counter (i, stream_id, step_lo, step_hi) under
  * key (seed_lo, seed_hi); its 4 outputs give two doubles in (0,1) from 52 bits

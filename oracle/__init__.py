@@ -146,6 +146,26 @@ class SMResult:
         self.n_walk = W
 
 
+_INDEX_CACHE = {}
+
+
+def _indexed(det_up, det_dn, c):
+    """preprocess.index_expansion, remembered by the content of its inputs."""
+    import hashlib
+    from . import preprocess
+    h = hashlib.sha256()
+    for a in (det_up, det_dn, c):
+        a = np.ascontiguousarray(a)
+        h.update(str((a.dtype, a.shape)).encode())
+        h.update(a.tobytes())
+    key = h.hexdigest()
+    if key not in _INDEX_CACHE:
+        if len(_INDEX_CACHE) > 8:
+            _INDEX_CACHE.clear()
+        _INDEX_CACHE[key] = preprocess.index_expansion(det_up, det_dn, c)
+    return _INDEX_CACHE[key]
+
+
 def sm_evaluate(wl, R=None, threshold=1e-3, n_threads=0, det_up=None, det_dn=None, c=None):
     """Psi and grad~Psi/Psi by the paper's Sherman-Morrison chain (Sec. 2.2).
 
@@ -153,14 +173,12 @@ def sm_evaluate(wl, R=None, threshold=1e-3, n_threads=0, det_up=None, det_dn=Non
     (``preprocess.index_expansion``); every walker runs its own chain.  The
     whole expansion is used (no per-walker excitation limit).
     """
-    from . import preprocess
     lib = _load()
     R = wl.R if R is None else R
     R = np.ascontiguousarray(R, dtype=np.float64)
     W, N = R.shape[0], wl.n_up + wl.n_dn
-    idx = preprocess.index_expansion(wl.det_up if det_up is None else det_up,
-                                     wl.det_dn if det_dn is None else det_dn,
-                                     wl.c if c is None else c)
+    idx = _indexed(wl.det_up if det_up is None else det_up,
+                   wl.det_dn if det_dn is None else det_dn, wl.c if c is None else c)
     uu = np.ascontiguousarray(idx["uniq_up"])
     ud = np.ascontiguousarray(idx["uniq_dn"])
     ri = np.ascontiguousarray(idx["row_i"], dtype=np.int32)

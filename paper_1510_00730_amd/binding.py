@@ -31,7 +31,8 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_get_kernel_times", "mdet_rng_fill", "mdet_vmc_step", "mdet_mlp_forward",
             "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step", "mdet_set_launch_config",
             "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune",
-            "mdet_norm_truncation", "mdet_set_method", "mdet_get_sm_counters"]
+            "mdet_norm_truncation", "mdet_set_method", "mdet_get_sm_counters",
+            "mdet_set_jastrow", "mdet_dmc_step"]
 METHOD_TABLE, METHOD_SM_CHAIN = 0, 1
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
 RNG_UNIFORM, RNG_NORMAL = 0, 1
@@ -100,6 +101,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_norm_truncation": (I32, [I32, I64, P, P, P, D, D, P, P, P, P]),
         "mdet_set_method": (I32, [P, I32, D, I32]),
         "mdet_get_sm_counters": (I32, [P, P]),
+        "mdet_set_jastrow": (I32, [P, I32, D, D, D]),
+        "mdet_dmc_step": (I32, [P, I64, D, D, D, I32, P, P, P, P, P, P, P, P, D, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -282,6 +285,21 @@ class Evaluator:
                                        _dptr(mlp_params), int(n_hidden), _dptr(R), _dptr(sign),
                                        _dptr(logabs), _dptr(gl), _dptr(noise), _dptr(uniform), Z,
                                        int(precision), _dptr(elocal), _dptr(accepted),
+                                       self._stream(stream)))
+
+    def set_jastrow(self, enable=True, b_ee=1.0, a_en=0.0, b_en=1.0):
+        """Slater-Jastrow trial function exp(J) Psi (see mdet_set_jastrow)."""
+        self._check(_LIB.mdet_set_jastrow(self._h, 1 if enable else 0, float(b_ee), float(a_en),
+                                          float(b_en)))
+
+    def dmc_step(self, R, sign, logabs, gl, elocal, weight, noise, uniform, comb_u, sums, accepted,
+                 tau=0.01, e_trial=0.0, nuclear_charge=None, precision=MDET_FP64, stream=None):
+        """One fixed-node DMC step on device tensors, in place (see mdet_dmc_step)."""
+        Z = float(self.n_up + self.n_dn) if nuclear_charge is None else float(nuclear_charge)
+        self._check(_LIB.mdet_dmc_step(self._h, R.shape[0], float(tau), float(e_trial), Z,
+                                       int(precision), _dptr(R), _dptr(sign), _dptr(logabs),
+                                       _dptr(gl), _dptr(elocal), _dptr(weight), _dptr(noise),
+                                       _dptr(uniform), float(comb_u), _dptr(sums), _dptr(accepted),
                                        self._stream(stream)))
 
     def mlp_forward(self, params, X, n_hidden, n_out, Y=None, stream=None):

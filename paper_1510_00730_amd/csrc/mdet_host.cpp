@@ -115,6 +115,10 @@ struct mdet_ctx {
     double sm_threshold = 1e-3;
     int32_t sm_chunk = 64;
     bool sm_ran = false;  // a chain evaluation has been queued since the last reset
+    bool jastrow_on = false;
+    JastrowParams jastrow{0.0, 0.0, 0.0};
+    // DMC work buffers (grow-only)
+    DevBuf q_eold, q_cum, q_src, q_R, q_sign, q_logabs, q_gl, q_el;
     hipStream_t own_stream = nullptr;
 
     // captured evaluations (mdet_eval_graph), keyed by every argument
@@ -190,6 +194,8 @@ struct mdet_ctx {
         m_gRp, m_gell, m_Jw, m_grad;
 
     void drop_vmc() {
+        for (DevBuf *b : {&q_eold, &q_cum, &q_src, &q_R, &q_sign, &q_logabs, &q_gl, &q_el})
+            b->release();
         for (DevBuf *b : {&v_Rp, &v_signp, &v_logabsp, &v_glp, &v_wsp, &v_signR, &v_logabsR, &v_glR,
                           &v_wsR, &m_X, &m_Xp, &m_h1a, &m_h2a, &m_h1b, &m_h2b, &m_O1, &m_O2,
                           &m_wh1, &m_wh2, &m_dO1, &m_dO2, &m_dX2, &m_gRp, &m_gell, &m_Jw, &m_grad})
@@ -639,6 +645,8 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.wstatus = wstatus_dev;
     hipEvent_t *ev = ctx->profiling ? ctx->next_event_set(kernels_of_method(a.method)) : nullptr;
     HIP_OK(launch_eval(a, st, ev));
+    if (ctx->jastrow_on)
+        launch_jastrow(n_walk, a.N, a.n_up, ctx->jastrow, R_dev, logabs_dev, gl_dev, st);
 }
 
 template <typename T>
@@ -1183,7 +1191,68 @@ mdet_status mdet_vmc_step(mdet_ctx *ctx, int64_t n_walk, int32_t proposal, doubl
         }
         launch_vmc_accept(n_walk, N, proposal, step, nuclear_charge, R_dev, sign_dev, logabs_dev,
                           gl_dev, Rp, ctx->v_signp.as<double>(), ctx->v_logabsp.as<double>(),
-                          ctx->v_glp.as<double>(), uniform_dev, o1, o2, elocal_dev, accepted_dev, st);
+                          ctx->v_glp.as<double>(), uniform_dev, o1, o2, elocal_dev, accepted_dev, 0,
+                          st);
+        HIP_OK(hipGetLastError());
+    });
+}
+
+mdet_status mdet_set_jastrow(mdet_ctx *ctx, int32_t enable, double b_ee, double a_en,
+                             double b_en) {
+    return guarded(ctx, [&] {
+        if (enable) {
+            require(std::isfinite(b_ee) && b_ee >= 0.0 && std::isfinite(a_en) &&
+                        std::isfinite(b_en) && b_en >= 0.0,
+                    MDET_EINVAL, "Jastrow parameters must be finite, b_ee and b_en >= 0");
+            ctx->jastrow = JastrowParams{b_ee, a_en, b_en};
+        }
+        ctx->jastrow_on = enable != 0;
+        ctx->drop_graphs();
+    });
+}
+
+mdet_status mdet_dmc_step(mdet_ctx *ctx, int64_t n_walk, double tau, double e_trial,
+                          double nuclear_charge, int32_t precision, double *R_dev,
+                          double *sign_dev, double *logabs_dev, double *gl_dev, double *elocal_dev,
+                          double *weight_dev, const double *noise_dev, const double *uniform_dev,
+                          double comb_u, double *sums_dev, int32_t *accepted_dev,
+                          void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context");
+        require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
+        require(tau > 0.0 && std::isfinite(tau) && std::isfinite(e_trial), MDET_EINVAL,
+                "tau must be positive, e_trial finite");
+        require(comb_u >= 0.0 && comb_u < 1.0, MDET_EINVAL, "comb_u must lie in [0, 1)");
+        require(precision == MDET_FP64 || precision == MDET_MIXED, MDET_EINVAL, "unknown precision");
+        require(n_walk >= 0 && n_walk <= (int64_t)1 << 24, MDET_EDIM, "n_walk out of range");
+        if (n_walk == 0) return;
+        require(R_dev && sign_dev && logabs_dev && gl_dev && elocal_dev && weight_dev && noise_dev &&
+                    uniform_dev && sums_dev && accepted_dev,
+                MDET_EINVAL, "null pointer");
+        HIP_OK(hipSetDevice(ctx->device));
+        const hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int N = ctx->n_up + ctx->n_dn;
+        ensure_vmc(ctx, n_walk, 0);
+        DmcWork d{};
+        double *e_old = grow<double>(ctx->q_eold, n_walk);
+        d.cum = grow<double>(ctx->q_cum, n_walk);
+        d.src = grow<int32_t>(ctx->q_src, n_walk);
+        d.R = grow<double>(ctx->q_R, n_walk * 3 * N);
+        d.sign = grow<double>(ctx->q_sign, n_walk);
+        d.logabs = grow<double>(ctx->q_logabs, n_walk);
+        d.gl = grow<double>(ctx->q_gl, n_walk * 4 * N);
+        d.elocal = grow<double>(ctx->q_el, n_walk);
+        double *Rp = ctx->v_Rp.as<double>();
+        launch_dmc_save(n_walk, elocal_dev, e_old, st);
+        launch_vmc_propose(n_walk, N, 1, tau, R_dev, gl_dev, noise_dev, Rp, st);
+        enqueue_eval(ctx, n_walk, Rp, precision, nullptr, ctx->v_signp.as<double>(),
+                     ctx->v_logabsp.as<double>(), ctx->v_glp.as<double>(), ctx->v_wsp.as<int32_t>(), st);
+        launch_vmc_accept(n_walk, N, 1, tau, nuclear_charge, R_dev, sign_dev, logabs_dev, gl_dev, Rp,
+                          ctx->v_signp.as<double>(), ctx->v_logabsp.as<double>(),
+                          ctx->v_glp.as<double>(), uniform_dev, nullptr, nullptr, elocal_dev,
+                          accepted_dev, 1, st);
+        launch_dmc_branch(n_walk, N, tau, e_trial, comb_u, e_old, accepted_dev, d, R_dev, sign_dev,
+                          logabs_dev, gl_dev, elocal_dev, weight_dev, sums_dev, st);
         HIP_OK(hipGetLastError());
     });
 }

@@ -172,6 +172,10 @@ uint32_t kernels_of_method(int method);
 // error.  If `events` is not null, events[2k] and events[2k + 1] are recorded
 // on the stream before and after kernel k (k < kNumKernels).
 hipError_t launch_eval(const KernelArgs &a, hipStream_t stream, hipEvent_t *events);
+// Sherman-Morrison chain method (its own source file): the chain pieces with
+// the exponent shift, and the derivative sums after the sparse combination.
+void launch_chain_pieces(const KernelArgs &a, hipStream_t stream);
+void launch_chain_deriv(const KernelArgs &a, hipStream_t stream);
 
 // ---------------------------------------------------------------- VMC and MLP
 constexpr double kMlpLogSigMin = -4.6051701859880914;  // ln 0.01
@@ -193,7 +197,7 @@ void launch_vmc_accept(int64_t W, int N, int proposal, double step, double Z, do
                        double *sign, double *logabs, double *gl, const double *Rp,
                        const double *signp, const double *logabsp, const double *glp,
                        const double *uniform, const float *o1, const float *o2, double *elocal,
-                       int32_t *accepted, hipStream_t st);
+                       int32_t *accepted, int fixed_node, hipStream_t st);
 void launch_gemm_f32(int M, int Nn, int K, const float *A, int a_rs, int a_cs, const float *B,
                      int b_rs, int b_cs, float *C, int c_rs, const float *bias, int act,
                      int accumulate, hipStream_t st);
@@ -215,5 +219,27 @@ void launch_esjd_chain(int64_t W, int N, const double *xi, const float *o1, cons
 void launch_esjd_loss(int64_t W, const double *Jw, double *out, hipStream_t st);
 void launch_adam(int64_t n, float *p, const float *g, float *m, float *v, float lr, float b1,
                  float b2, float eps, int t, hipStream_t st);
+
+// ------------------------------------------------------------ Jastrow and DMC
+struct JastrowParams {
+    double b_ee;  // electron-electron Pade denominator
+    double a_en;  // electron-nucleus amplitude (-Z: nuclear cusp; 0: no term)
+    double b_en;  // electron-nucleus Pade denominator
+};
+
+// DMC work buffers (device), W walkers
+struct DmcWork {
+    double *cum;     // [W] cumulative branching weights
+    int32_t *src;    // [W] selected walker of each new slot
+    double *R, *sign, *logabs, *gl, *elocal;  // gathered state
+};
+
+void launch_jastrow(int64_t W, int N, int n_up, const JastrowParams &p, const double *R,
+                    double *logabs, double *gl, hipStream_t st);
+void launch_dmc_save(int64_t W, const double *elocal, double *e_old, hipStream_t st);
+void launch_dmc_branch(int64_t W, int N, double tau, double e_trial, double comb_u,
+                       const double *e_old, const int32_t *accepted, DmcWork &d, double *R,
+                       double *sign, double *logabs, double *gl, double *elocal, double *weight,
+                       double *sums, hipStream_t st);
 
 }  // namespace mdet

@@ -19,7 +19,7 @@
 // Reductions are done in a fixed order, so FP64 results are bitwise
 // reproducible run to run.
 
-#include "mdet_internal.h"
+#include "mdet_device.h"
 
 #include <math.h>
 
@@ -30,9 +30,7 @@ namespace mdet {
 
 namespace {
 
-constexpr int kBlock = 256;
 static_assert(kAdjChunkDets % kBlock == 0, "whole determinants per thread and chunk");
-constexpr int kMaxN = MDET_MAX_SPIN_ELEC;
 
 __device__ __forceinline__ double pow2(int k) { return ldexp(1.0, k); }
 
@@ -165,9 +163,12 @@ __device__ double cofactor(const double *m, int s, int a, int b) {
     return ((a + b) & 1) ? -d : d;
 }
 
+// (fixed trip count: the descriptor's fields stay in registers)
 __device__ __forceinline__ int delta_exponent(const DetDesc &D, const int *Ex, const int *occ0) {
     int dx = 0;
-    for (int a = 0; a < D.s; ++a) dx += Ex[D.p[a]] - Ex[occ0[D.h[a]]];
+#pragma unroll
+    for (int a = 0; a < MDET_MAX_DEGREE; ++a)
+        if (a < D.s) dx += Ex[D.p[a]] - Ex[occ0[D.h[a]]];
     return dx;
 }
 
@@ -285,20 +286,6 @@ __device__ __forceinline__ double det_lu(const double *m) {
         }
     }
     return det;
-}
-
-// Offsets of the walker-major vectors R, u, v: entry d of spin sp for walker
-// w sits at w * (Upad + Vpad) + (sp ? Upad : 0) + d.
-__device__ __forceinline__ size_t rv_index(const KernelArgs &a, int sp, int d, int w) {
-    return (size_t)w * (size_t)(a.wk.Upad + a.wk.Vpad) + (sp ? (size_t)a.wk.Upad : 0) + d;
-}
-
-// psi of walker w: the row-split partial sums of the sparse combination
-// (accumulated in FP64 in both precisions), added in a fixed order
-__device__ __forceinline__ double psi_value(const KernelArgs &a, int w) {
-    double s = 0.0;
-    for (int k = 0; k < a.psi_nparts; ++k) s += a.wk.psi64[(size_t)w * kPsiParts + k];
-    return s;
 }
 
 // s x s excitation matrix M[a][b] = T[h_a][p_b], compile-time s
@@ -436,94 +423,6 @@ __device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int
 // that use it rebuild it in LDS from X and the orbitals (build_table).
 // ---------------------------------------------------------------------------
 namespace {
-
-// LDS hand-off between the lanes of one wave (no block barrier)
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// In-place Gauss-Jordan inversion with partial pivoting of an n x n matrix
-// A by the first 16 lanes of one wave, lane i holding row i in r[].  Rows are
-// never exchanged: the pivot of column j is the unused lane with the largest
-// |entry| (lowest lane on ties), and the lane that pivots column c ends up
-// holding row c of A^-1 with column plane[j] in slot j.  The pivot search and
-// the pivot row go through the wave's LDS scratch sc (at least 2 kMaxN + 1
-// doubles).  The inverse is written to Xo (LDS, row-major, leading dimension
-// ldx); det A = mant 2^ex (mant signed).  Returns false on an exactly zero,
-// infinite or NaN pivot.
-__device__ __forceinline__ bool lane_gj_core(int n, int lane, double (&r)[kMaxN], double *Xo,
-                                             int ldx, double *sc, double &mant_out, int &ex_out) {
-    double *cand = sc, *prow = sc + kMaxN;  // |candidates| per lane, normalised pivot row
-    int pc = -1;
-    int plane[kMaxN];
-    double mant = 1.0;
-    int ex = 0;
-#pragma unroll
-    for (int j = 0; j < kMaxN; ++j) {
-        if (j >= n) break;
-        if (lane < kMaxN) {
-            double v = (pc < 0 && lane < n) ? fabs(r[j]) : -1.0;
-            if (v != v) v = INFINITY;  // NaN: pick it, then fail below
-            cand[lane] = v;
-        }
-        wave_lds_sync();
-        double best = cand[0];
-        int id = 0;
-#pragma unroll
-        for (int l = 1; l < kMaxN; ++l) {
-            const double v = cand[l];
-            if (v > best) {
-                best = v;
-                id = l;
-            }
-        }
-        id = __builtin_amdgcn_readfirstlane(id);
-        if (!(best > 0.0) || !(best < INFINITY)) return false;
-        plane[j] = id;
-        const double f = r[j];
-        if (lane == id) {
-            const double rinv = 1.0 / f;
-            pc = j;
-            r[j] = 1.0;
-#pragma unroll
-            for (int k = 0; k < kMaxN; ++k) {
-                r[k] *= rinv;
-                if (k < n) prow[k] = r[k];
-            }
-            prow[kMaxN] = f;
-        }
-        wave_lds_sync();
-        const double piv = prow[kMaxN];
-        mant *= piv;
-        int kk;
-        mant = frexp(mant, &kk);
-        ex += kk;
-        if (lane != id) {
-            r[j] = 0.0;
-#pragma unroll
-            for (int k = 0; k < kMaxN; ++k)
-                if (k < n) r[k] -= f * prow[k];
-        }
-        wave_lds_sync();  // cand / prow are rewritten by the next step
-    }
-    // det A = det(Q) prod piv, Q the permutation j -> plane[j]
-    int inv = 0;
-#pragma unroll
-    for (int i = 0; i < kMaxN; ++i)
-#pragma unroll
-        for (int j = i + 1; j < kMaxN; ++j)
-            if (j < n && plane[i] > plane[j]) ++inv;
-    mant_out = (inv & 1) ? -mant : mant;
-    ex_out = ex;
-    if (pc >= 0) {
-#pragma unroll
-        for (int j = 0; j < kMaxN; ++j)
-            if (j < n) Xo[pc * ldx + plane[j]] = r[j];
-    }
-    return true;
-}
 
 // The same for A in LDS (row-major, ld n) and Xo with ld n; logabs and sign
 // receive ln|det A| and its sign.
@@ -1290,8 +1189,9 @@ __device__ __forceinline__ void lu_regs(double (&a)[K][K], int (&perm)[K], doubl
 // occupied orbital of slot c for determinant D (reference with holes replaced)
 __device__ __forceinline__ int slot_orbital(const DetDesc &D, const int *occ0, int c) {
     int o = occ0[c];
-    for (int t = 0; t < D.s; ++t)
-        if (D.h[t] == c) o = D.p[t];
+#pragma unroll
+    for (int t = 0; t < MDET_MAX_DEGREE; ++t)
+        if (t < D.s && D.h[t] == c) o = D.p[t];
     return o;
 }
 
@@ -1364,7 +1264,7 @@ __device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, i
                                   const int *occ0, const double *P0, const double *Gs,
                                   const double *Gg, const int *Ex, int d0, int d1,
                                   double *red) {
-    const int M = a.M, n = S.n, N = a.N;
+    const int M = a.M, n = S.n;
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const int Kx = a.wk.K[(size_t)w * 2 + sp];
     const bool mixed = a.precision == MDET_MIXED;
@@ -1554,287 +1454,6 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a) {
             for (int v = 0; v < kDirectBlock / 64; ++v) t += red[v * 4 * K + e * 4 + q];
             a.wk.dpart[(((size_t)w * kDirectSplitMax + part) * N + S.e0) * 4 + i] = t;
         }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// The paper's own method (Sec. 2.2-2.3): a Sherman-Morrison chain over the
-// distinct determinants in the sorted order of Eq. (comp).  One block per
-// (walker, spin) stages that spin's scaled orbitals in LDS; each of its waves
-// takes pieces of sm_chunk consecutive determinants: it factorises the first
-// one, then reaches every next determinant by column substitutions on the
-// inverse held in LDS.  Per determinant it writes the determinant as mantissa
-// and exponent (like the direct-LU fallback) and the ratios
-// grad~_e D / D = sum_c X[c][e] grad~phi_{col_c}(r_e).
-// The inverse lives in a zero-padded 16 x 16 LDS tile, so every loop runs to
-// 16 without per-step guards and vectors reach the lanes through LDS
-// broadcasts (few scalar instructions).  Lane c < 16 owns row c of the
-// products, lane 16 g + e updates column e of rows g, g + 4, g + 8, g + 12,
-// lane 4 e + q forms the derivative ratio (e, q).
-// ---------------------------------------------------------------------------
-constexpr int kSmWaves = 8;
-constexpr int kSmLd = kMaxN + 1;  // LDS row pitch of the inverse tile
-
-// FP64 lane broadcast from a wave-uniform lane index
-__device__ __forceinline__ double readlane_d(double v, int l) {
-    const uint64_t b = __double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
-// Orbital planes staged per block: all five (values and derivatives) when
-// they fit in 96 KB, else the values only (derivatives then read from HBM).
-__host__ __device__ __forceinline__ int sm_planes(int nmax, int M) {
-    return 5 * (size_t)nmax * M * sizeof(double) <= 96 * 1024 ? 5 : 1;
-}
-// LDS doubles of one chain wave: inverse tile, phi_p, update factors,
-// column orbitals (16 ints), Gauss-Jordan scratch
-constexpr int kSmWaveDoubles = kMaxN * kSmLd + kMaxN + kMaxN + kMaxN / 2 + 2 * kMaxN + 2;
-__host__ __device__ __forceinline__ size_t sm_block_doubles(int nmax, int M) {
-    return (size_t)sm_planes(nmax, M) * nmax * M + (M + 1) / 2 + (size_t)kSmWaves * kSmWaveDoubles;
-}
-
-template <typename F>
-__global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg) {
-    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x, lane = tid & 63;
-    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const SpinDev &S = a.sp[sp];
-    const int n = S.n, M = a.M, nmax = a.nmax;
-    const int planes = sm_planes(nmax, M);
-    const size_t ws = (size_t)w * 2 + sp;
-    extern __shared__ double lds[];
-    double *Pst = lds;                                   // [planes][n][M] scaled orbitals
-    int *Ex = (int *)(Pst + (size_t)planes * nmax * M);  // [M] column exponents
-    double *Xs = (double *)Ex + (M + 1) / 2 + (size_t)wv * kSmWaveDoubles;  // X[c][e] at c*kSmLd+e
-    double *pv = Xs + kMaxN * kSmLd;                     // [16] phi_p at the electrons
-    double *fv = pv + kMaxN;                             // [16] update factors
-    int *cv = (int *)(fv + kMaxN);                       // [16] column orbitals (0 beyond n)
-    double *sc = (double *)(cv + kMaxN);                 // Gauss-Jordan scratch
-    const double *Pg = a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M;  // [e][5][M] unscaled
-    for (int m = tid; m < M; m += 64 * kSmWaves) Ex[m] = a.wk.E[ws * M + m];
-    __syncthreads();
-    for (int i = tid; i < planes * n * M; i += 64 * kSmWaves) {
-        const int q = i / (n * M), r = i - q * (n * M), e = r / M, m = r - e * M;
-        Pst[i] = ldexp(Pg[((size_t)e * 5 + q) * M + m], -Ex[m]);
-    }
-    __syncthreads();
-    const double thr = a.sm_threshold;
-    const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
-    const int L = a.sm_chunk, npieces = (S.U + L - 1) / L;
-    const int C4 = 4 * nmax;
-    F *gout = smg + ws * (size_t)a.wk.Umax * C4;
-    const int ge = lane & 15, gg = lane >> 4;      // update role: column ge, rows gg + 4 j
-    const int de = min(lane >> 2, max(n - 1, 0));  // derivative role: electron (clamped)
-    const int dq = 1 + (lane & 3);
-    int kmax = INT_MIN;
-    unsigned long long nsub = 0, ninv = 0, nfail = 0, nstart = 0;
-
-    for (int piece = wv; piece < npieces; piece += kSmWaves) {
-        const int p0 = piece * L, p1 = min(p0 + L, S.U);
-        int colv = 0;          // lane c < n: orbital in column slot c
-        double mant = 0.0;     // det of the scaled matrix = mant 2^ex (sign in mant)
-        int ex = 0, esum = 0;  // esum: sum of the column exponents of the current columns
-        bool have = false;
-
-        // factorise the determinant at chain position pos from scratch
-        auto restart = [&](int pos) {
-            const int occ_l = lane < n ? (int)S.sm_occ[(size_t)pos * n + lane] : 0;
-            for (int i = lane; i < kMaxN * kSmLd; i += 64) Xs[i] = 0.0;
-            if (lane < kMaxN) cv[lane] = occ_l;
-            double rr[kMaxN];
-#pragma unroll
-            for (int c = 0; c < kMaxN; ++c) rr[c] = 0.0;
-            if (lane < n) {
-#pragma unroll
-                for (int c = 0; c < kMaxN; ++c)
-                    if (c < n) rr[c] = Pst[lane * M + __shfl(occ_l, c, 64)];
-            }
-            int es = lane < n ? Ex[occ_l] : 0;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) es += __shfl_xor(es, off, 64);
-            colv = occ_l;
-            esum = es;
-            wave_lds_sync();
-            have = lane_gj_core(n, lane, rr, Xs, kSmLd, sc, mant, ex);
-            wave_lds_sync();
-        };
-
-        // one column substitution h -> p; false if |ratio| < thr
-        auto substitute = [&](int h, int p) -> bool {
-            const uint64_t hb = __ballot(lane < n && colv == h);
-            if (hb == 0) return false;  // not reached for a consistent list
-            const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(hb));
-            if (lane < kMaxN) pv[lane] = lane < n ? Pst[lane * M + p] : 0.0;
-            wave_lds_sync();
-            double w0 = 0.0, w1 = 0.0;  // lane c < 16: (X phi_p)[c]
-            if (lane < kMaxN) {
-#pragma unroll
-                for (int e = 0; e < kMaxN; e += 2) {
-                    w0 += Xs[lane * kSmLd + e] * pv[e];
-                    w1 += Xs[lane * kSmLd + e + 1] * pv[e + 1];
-                }
-            }
-            const double wc = w0 + w1;
-            const double r = readlane_d(wc, k);
-            if (!(fabs(r) >= thr)) return false;
-            // X <- X - (X u)(row k of X) / r with X u = X phi_p - e_k
-            if (lane < kMaxN) fv[lane] = (wc - (lane == k ? 1.0 : 0.0)) / r;
-            const double xk = Xs[k * kSmLd + ge];
-            wave_lds_sync();
-#pragma unroll
-            for (int j = 0; j < kMaxN / 4; ++j) {
-                const int c = gg + 4 * j;
-                Xs[c * kSmLd + ge] -= fv[c] * xk;
-            }
-            if (lane == k) cv[k] = p;
-            // the sorting permutation changes parity once per other column between h and p
-            const int lo = min(h, p), hi = max(h, p);
-            const uint64_t between = __ballot(lane < n && lane != k && colv > lo && colv < hi);
-            mant *= (__popcll(between) & 1) ? -r : r;
-            int kk;
-            mant = frexp(mant, &kk);
-            ex += kk;
-            esum += Ex[p] - Ex[h];
-            if (lane == k) colv = p;
-            wave_lds_sync();
-            return true;
-        };
-
-        for (int win = p0; win < p1; win += 64) {
-            // per-determinant lists of the next (up to) 64 positions, one per lane
-            const int pl = win + lane;
-            const bool in = pl < p1;
-            const int exec_l = in ? S.sm_exec[pl] : 0;
-            const int off_l = in ? S.sm_off[pl] : 0;
-            const int offn_l = in ? S.sm_off[pl + 1] : 0;
-            const int deg_l = in ? (int)S.desc[exec_l].s : 0;
-            const int wend = min(win + 64, p1);
-            for (int pos = win; pos < wend; ++pos) {
-                const int j = pos - win;
-                bool fresh = pos == p0 || !have;  // factorise this determinant from scratch
-                if (!fresh) {
-                    const int s0 = __builtin_amdgcn_readlane(off_l, j);
-                    const int ns = __builtin_amdgcn_readlane(offn_l, j) - s0;
-                    const uint32_t pr_l = lane < ns ? S.sm_sub[s0 + lane] : 0u;
-                    uint32_t todo = ns >= 32 ? 0xffffffffu : ((1u << ns) - 1u);
-                    while (todo) {
-                        uint32_t left = todo;
-                        int done = 0;
-                        for (uint32_t bits = todo; bits; bits &= bits - 1) {
-                            const int i = __builtin_ctz(bits);
-                            const uint32_t pr = __builtin_amdgcn_readlane(pr_l, i);
-                            if (substitute((int)(pr & 0xffffu), (int)(pr >> 16))) {
-                                left &= ~(1u << i);
-                                ++done;
-                                ++nsub;
-                            } else {
-                                ++nfail;
-                            }
-                        }
-                        todo = left;
-                        if (todo && done == 0) {  // no progress: factorise from scratch
-                            fresh = true;
-                            break;
-                        }
-                    }
-                }
-                if (fresh) {
-                    restart(pos);
-                    if (pos == p0) ++nstart;
-                    else ++ninv;
-                }
-                const int d = __builtin_amdgcn_readlane(exec_l, j);
-                const bool keep = have && __builtin_amdgcn_readlane(deg_l, j) <= dmax;
-                if (lane < 4 * n) {
-                    double t0 = 0.0, t1 = 0.0;
-                    if (planes == 5) {
-                        const double *G = Pst + ((size_t)dq * n + de) * M;
-#pragma unroll
-                        for (int c = 0; c < kMaxN; c += 2) {
-                            t0 += Xs[c * kSmLd + de] * G[cv[c]];
-                            t1 += Xs[(c + 1) * kSmLd + de] * G[cv[c + 1]];
-                        }
-                    } else {
-                        const double *G = Pg + ((size_t)de * 5 + dq) * M;
-#pragma unroll
-                        for (int c = 0; c < kMaxN; c += 2) {
-                            t0 += Xs[c * kSmLd + de] * ldexp(G[cv[c]], -Ex[cv[c]]);
-                            t1 += Xs[(c + 1) * kSmLd + de] * ldexp(G[cv[c + 1]], -Ex[cv[c + 1]]);
-                        }
-                    }
-                    gout[(size_t)d * C4 + lane] = keep ? (F)(t0 + t1) : (F)0;
-                }
-                if (lane == 0) {
-                    const size_t o = rv_index(a, sp, d, w);
-                    a.wk.R64[o] = keep ? mant : 0.0;
-                    a.wk.Rexp[o] = keep ? ex + esum : INT_MIN;
-                }
-                if (keep && mant != 0.0) kmax = max(kmax, ex + esum);
-            }
-        }
-    }
-    if (lane == 0) {
-        if (kmax != INT_MIN) atomicMax(&a.wk.Kmax[ws], kmax);
-        atomicAdd(&a.wk.smstat[0], nsub);
-        atomicAdd(&a.wk.smstat[1], ninv);
-        atomicAdd(&a.wk.smstat[2], nfail);
-        atomicAdd(&a.wk.smstat[3], nstart);
-    }
-}
-
-// shift the chain's determinants by the (walker, spin) maximum exponent:
-// one block per (walker, spin)
-__global__ void __launch_bounds__(kBlock) k_sm_scale(KernelArgs a) {
-    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
-    const size_t ws = (size_t)w * 2 + sp;
-    int K = a.wk.Kmax[ws];
-    if (K == INT_MIN) K = 0;
-    if (threadIdx.x == 0) {
-        a.wk.K[ws] = K;
-        a.wk.logdet0[ws] = 0.0;
-        a.wk.sign0[ws] = 1.0;
-        a.wk.flag[ws] = 0;
-    }
-    for (int d = threadIdx.x; d < a.sp[sp].U; d += kBlock) {
-        const size_t o = rv_index(a, sp, d, w);
-        const int e = a.wk.Rexp[o];
-        const double r = (e == INT_MIN) ? 0.0 : ldexp(a.wk.R64[o], e - K);
-        if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
-        else a.wk.R64[o] = r;
-    }
-}
-
-// grad~_e Psi / Psi = sum_d R_d w_d (grad~_e D_d / D_d) / psi with w = u (up)
-// or v (down): one block per (walker, spin); thread t reads component
-// t mod 4n of determinants t / 4n + k (256 / 4n), so each pass reads a
-// contiguous run of the stored ratios.
-template <typename F>
-__global__ void __launch_bounds__(kBlock) k_sm_deriv(KernelArgs a, const F *R, const F *uv,
-                                                     const F *smg) {
-    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
-    const SpinDev &S = a.sp[sp];
-    const int n = S.n, cn = 4 * n, C4 = 4 * a.nmax;
-    if (cn == 0) return;
-    const size_t ws = (size_t)w * 2 + sp;
-    const int per = kBlock / cn;
-    __shared__ double red[kBlock];
-    double s = 0.0;
-    if (tid < per * cn) {
-        const int k = tid % cn;
-        const F *g = smg + ws * (size_t)a.wk.Umax * C4;
-        for (int d = tid / cn; d < S.U; d += per) {
-            const size_t o = rv_index(a, sp, d, w);
-            s += ((double)R[o] * (double)uv[o]) * (double)g[(size_t)d * C4 + k];
-        }
-    }
-    red[tid] = s;
-    __syncthreads();
-    if (tid < cn) {
-        double t = 0.0;
-        for (int j = 0; j < per; ++j) t += red[j * cn + tid];
-        const double psi = psi_value(a, w);
-        a.gl_out[((size_t)w * a.N + S.e0) * 4 + tid] = t / psi;
     }
 }
 
@@ -2111,10 +1730,7 @@ hipError_t launch_chain(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     };
     const bool mixed = a.precision == MDET_MIXED;
     mark(7, false);
-    const size_t lds_sm = sizeof(double) * sm_block_doubles(a.nmax, a.M);
-    if (mixed) k_sm_chain<float><<<g2, dim3(64 * kSmWaves), lds_sm, st>>>(a, a.wk.smg32);
-    else k_sm_chain<double><<<g2, dim3(64 * kSmWaves), lds_sm, st>>>(a, a.wk.smg64);
-    k_sm_scale<<<g2, blk, 0, st>>>(a);
+    launch_chain_pieces(a, st);
     mark(7, true);
     mark(3, false);
     const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
@@ -2129,8 +1745,7 @@ hipError_t launch_chain(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
             a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
     mark(3, true);
     mark(8, false);
-    if (mixed) k_sm_deriv<float><<<g2, blk, 0, st>>>(a, a.wk.R32, a.wk.uv32, a.wk.smg32);
-    else k_sm_deriv<double><<<g2, blk, 0, st>>>(a, a.wk.R64, a.wk.uv64, a.wk.smg64);
+    launch_chain_deriv(a, st);
     mark(8, true);
     mark(6, false);
     k_finalize<<<dim3((unsigned)(((int64_t)W * 4 * a.N + kBlock - 1) / kBlock)), blk, 0, st>>>(a);

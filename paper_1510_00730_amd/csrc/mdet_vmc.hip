@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kVBlock) k_vmc_accept(int64_t W, int N, int pr
                                                         const double *logabsp, const double *glp,
                                                         const double *uniform, const float *o1,
                                                         const float *o2, double *elocal,
-                                                        int32_t *accepted) {
+                                                        int32_t *accepted, int fixed_node) {
     const int64_t w = (int64_t)blockIdx.x * kVBlock + threadIdx.x;
     if (w >= W) return;
     const int n3 = 3 * N, n4 = 4 * N;
@@ -134,6 +134,8 @@ __global__ void __launch_bounds__(kVBlock) k_vmc_accept(int64_t W, int N, int pr
     bool ok;
     if (signp[w] == 0.0) {
         ok = false;  // never move onto a node
+    } else if (fixed_node && signp[w] != sign[w]) {
+        ok = false;  // never cross a node (diffusion Monte Carlo)
     } else if (sign[w] == 0.0) {
         ok = true;   // leave a node whatever the ratio
     } else {
@@ -364,10 +366,10 @@ void launch_vmc_accept(int64_t W, int N, int proposal, double step, double Z, do
                        double *sign, double *logabs, double *gl, const double *Rp,
                        const double *signp, const double *logabsp, const double *glp,
                        const double *uniform, const float *o1, const float *o2, double *elocal,
-                       int32_t *accepted, hipStream_t st) {
+                       int32_t *accepted, int fixed_node, hipStream_t st) {
     k_vmc_accept<<<g1(W), dim3(kVBlock), 0, st>>>(W, N, proposal, step, Z, R, sign, logabs, gl,
                                                    Rp, signp, logabsp, glp, uniform, o1, o2,
-                                                   elocal, accepted);
+                                                   elocal, accepted, fixed_node);
 }
 
 void launch_gemm_f32(int M, int Nn, int K, const float *A, int a_rs, int a_cs, const float *B,
