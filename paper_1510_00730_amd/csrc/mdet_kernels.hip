@@ -163,12 +163,9 @@ __device__ double cofactor(const double *m, int s, int a, int b) {
     return ((a + b) & 1) ? -d : d;
 }
 
-// (fixed trip count: the descriptor's fields stay in registers)
 __device__ __forceinline__ int delta_exponent(const DetDesc &D, const int *Ex, const int *occ0) {
     int dx = 0;
-#pragma unroll
-    for (int a = 0; a < MDET_MAX_DEGREE; ++a)
-        if (a < D.s) dx += Ex[D.p[a]] - Ex[occ0[D.h[a]]];
+    for (int a = 0; a < D.s; ++a) dx += Ex[D.p[a]] - Ex[occ0[D.h[a]]];
     return dx;
 }
 
@@ -1189,9 +1186,8 @@ __device__ __forceinline__ void lu_regs(double (&a)[K][K], int (&perm)[K], doubl
 // occupied orbital of slot c for determinant D (reference with holes replaced)
 __device__ __forceinline__ int slot_orbital(const DetDesc &D, const int *occ0, int c) {
     int o = occ0[c];
-#pragma unroll
-    for (int t = 0; t < MDET_MAX_DEGREE; ++t)
-        if (t < D.s && D.h[t] == c) o = D.p[t];
+    for (int t = 0; t < D.s; ++t)
+        if (D.h[t] == c) o = D.p[t];
     return o;
 }
 

@@ -53,6 +53,19 @@ def test_indexing_bit_exact_vs_oracle(cid):
     assert sum(st.n_by_degree_up) == st.n_uniq_up
 
 
+@pytest.mark.parametrize("n_mo", [200, 300, 512])
+def test_indexing_bit_exact_many_words(n_mo):
+    """Encodings of 4, 5 and 8 words per determinant (orbitals beyond 128)."""
+    from gen.workloads import make_custom
+    wl = make_custom(9, 8, n_mo, 2, 400, 300, (1, 2, 3, 4), 4000, 4, seed=n_mo)
+    assert wl.n_int == (n_mo + 63) // 64 >= 4
+    ev = host_ctx(wl)
+    got = ev.indexing()
+    ref = pp.index_expansion(wl.det_up, wl.det_dn, wl.c)
+    for k in ("uniq_up", "uniq_dn", "row_i", "col_j", "src_pos"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
 @pytest.mark.slow
 def test_indexing_bit_exact_largest_config():
     wl = make_config(4)

@@ -179,6 +179,20 @@ def test_cauchy_binet_full_ci_on_gpu():
         assert np.abs(gl[w] - g).max() < 1e-8 * (1 + np.abs(g).max())
 
 
+@pytest.mark.parametrize("n_mo", [200, 512])
+def test_fp64_parity_many_words(n_mo):
+    """Orbitals beyond 128: 4- and 8-word encodings, excitations up to degree 4."""
+    log(f"[parity] {n_mo} orbitals ({(n_mo + 63) // 64} words), 9+8 electrons, FP64 and mixed")
+    wl = make_custom(9, 8, n_mo, 2, 400, 300, (1, 2, 3, 4), 4000, 64, seed=n_mo)
+    ev = evaluator(wl)
+    ref = oracle.evaluate(wl, n_threads=16)
+    for prec, tol in ((mdet.MDET_FP64, FP64_TOL), (mdet.MDET_MIXED, MIXED_TOL)):
+        sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=prec)
+        ep, eg = scaled_errors(ref, sign, logabs, gl)
+        summary(f"M={n_mo} precision {prec}", ep, eg, ws)
+        assert ep.max() <= tol and eg.max() <= tol
+
+
 def test_indexing_on_device_context_matches_oracle():
     from oracle import preprocess as pp
     wl = workload(3)
