@@ -49,13 +49,18 @@ enum {
     MDET_ENOMEM = -7,      /* device or host allocation failed                       */
     MDET_EHIP = -8,        /* a HIP runtime call failed                              */
     MDET_ESTATE = -9,      /* call order violated (e.g. eval before set_expansion)   */
-    MDET_EDEGREE = -10     /* excitation degree above MDET_MAX_DEGREE                */
+    MDET_EDEGREE = -10     /* table-method evaluation of an expansion with an
+                              excitation degree above MDET_MAX_DEGREE               */
 };
 
 enum { MDET_FP64 = 0, MDET_MIXED = 1 };
 
 /* Largest excitation degree (holes = particles) of a spin determinant relative
- * to the reference spin determinant that set_expansion accepts. */
+ * to the reference spin determinant that the table method evaluates, and the
+ * largest per-walker degree limit.  set_expansion accepts any degree; an
+ * expansion holding a higher degree is evaluated by MDET_METHOD_SM_CHAIN
+ * only (the chain substitutes columns between consecutive determinants and
+ * has no degree limit), without per-walker degree limits. */
 #define MDET_MAX_DEGREE 4
 /* Largest number of electrons of one spin. */
 #define MDET_MAX_SPIN_ELEC 16
@@ -105,7 +110,7 @@ mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim,
  * the earliest one on ties).
  * det_up, det_dn: uint64 [n_det][n_int] host; c: double [n_det] host.
  * Requires mdet_init_orbitals first.  Errors: MDET_ESPIN, MDET_EORBITAL,
- * MDET_EPOPCOUNT, MDET_EDUPLICATE, MDET_EDEGREE, MDET_EDIM (n_dn < 1,
+ * MDET_EPOPCOUNT, MDET_EDUPLICATE, MDET_EDIM (n_dn < 1,
  * n_up > MDET_MAX_SPIN_ELEC, n_up > n_mo, n_up * n_mo > 6144 (the per-walker tables
  * of the derivative kernel must fit in LDS), or n_det
  * outside 1..2^30-1).
@@ -170,6 +175,9 @@ mdet_status mdet_norm_truncation(int32_t n_int, int64_t n_det, const uint64_t *d
  *  hip_stream   hipStream_t (NULL = default stream).
  * Asynchronous on hip_stream.  Library work buffers grow to the largest
  * n_walk seen and are reused; calls on one context must not overlap.
+ * Errors: MDET_EDEGREE when the expansion holds an excitation degree above
+ * MDET_MAX_DEGREE and the method is the table method; MDET_EINVAL for
+ * max_degree_dev with such an expansion.
  */
 mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev,
                               int32_t precision, const int8_t *max_degree_dev,

@@ -70,6 +70,8 @@ struct SpinHost {
     std::vector<int32_t> pub_of;     // exec -> public
     std::vector<DetDesc> desc;       // exec order
     int64_t n_by_degree[MDET_MAX_DEGREE + 1] = {0};
+    bool high_degree = false;  // some determinant above MDET_MAX_DEGREE (chain method only)
+    int64_t n_above = 0;
     std::vector<int32_t> adj_off, chunk_det, gptr;
     std::vector<uint16_t> gpos;
     // Sherman-Morrison chain lists (public order = chain order)
@@ -334,32 +336,34 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
         const uint64_t *d = s.uniq.data() + i * n_int;
         DetDesc D;
         std::memset(&D, 0, sizeof(D));
+        // holes and particles; above MDET_MAX_DEGREE only the degree is kept
+        // (such a determinant is evaluated by the chain method only)
         int nh = 0, np = 0;
         for (int c = 0; c < n; ++c) {
             const int m = s.occ0[c];
             if (!((d[m >> 6] >> (m & 63)) & 1ull)) {
-                if (nh >= MDET_MAX_DEGREE)
-                    throw Status(MDET_EDEGREE, "excitation degree above " +
-                                                   std::to_string(MDET_MAX_DEGREE));
-                D.h[nh++] = (uint8_t)c;
+                if (nh < MDET_MAX_DEGREE) D.h[nh] = (uint8_t)c;
+                ++nh;
             }
         }
         for (int32_t m : occupied(d, n_int)) {
             if (slot_of[m] < 0) {
-                if (np >= MDET_MAX_DEGREE)
-                    throw Status(MDET_EDEGREE, "excitation degree above " +
-                                                   std::to_string(MDET_MAX_DEGREE));
-                D.p[np++] = (uint16_t)m;
+                if (np < MDET_MAX_DEGREE) D.p[np] = (uint16_t)m;
+                ++np;
             }
         }
         D.s = (uint8_t)nh;
-        // sign of the permutation sorting occ0 with h[a] -> p[a] substituted in place
-        std::vector<int32_t> lst(s.occ0);
-        for (int a = 0; a < nh; ++a) lst[D.h[a]] = D.p[a];
-        int inv = 0;
-        for (int x = 0; x < n; ++x)
-            for (int y = x + 1; y < n; ++y) inv += lst[x] > lst[y];
-        D.eps = (inv & 1) ? -1 : 1;
+        if (nh > MDET_MAX_DEGREE) {
+            s.high_degree = true;
+        } else {
+            // sign of the permutation sorting occ0 with h[a] -> p[a] substituted in place
+            std::vector<int32_t> lst(s.occ0);
+            for (int a = 0; a < nh; ++a) lst[D.h[a]] = D.p[a];
+            int inv = 0;
+            for (int x = 0; x < n; ++x)
+                for (int y = x + 1; y < n; ++y) inv += lst[x] > lst[y];
+            D.eps = (inv & 1) ? -1 : 1;
+        }
         pub_desc[i] = D;
         deg[i] = nh;
     }
@@ -370,10 +374,19 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
     s.exec_of.assign(s.U, 0);
     s.desc.resize(s.U);
     for (int k = 0; k <= MDET_MAX_DEGREE; ++k) s.n_by_degree[k] = 0;
+    s.n_above = 0;
     for (int64_t e = 0; e < s.U; ++e) {
         s.exec_of[s.pub_of[e]] = (int32_t)e;
         s.desc[e] = pub_desc[s.pub_of[e]];
-        s.n_by_degree[s.desc[e].s]++;
+        if (s.desc[e].s <= MDET_MAX_DEGREE) s.n_by_degree[s.desc[e].s]++;
+        else ++s.n_above;
+    }
+    if (s.high_degree) {  // no table-method structures: one empty adjugate chunk
+        s.adj_off.assign(s.U + 1, 0);
+        s.chunk_det.assign({0, (int32_t)s.U});
+        s.gptr.assign((size_t)n * n_mo + 1, 0);
+        s.gpos.assign(1, 0);
+        return;
     }
     // Derivative aggregation: the s*s scaled adjugate entries of determinant d
     // occupy slots adj_off[d] + a*s + b of a staging buffer; determinants are
@@ -575,6 +588,13 @@ void ensure_chain(mdet_ctx *c, int64_t W) {
 void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
                   const int8_t *max_degree_dev, double *sign_dev, double *logabs_dev,
                   double *gl_dev, int32_t *wstatus_dev, hipStream_t st) {
+    const bool high = ctx->sp[0].high_degree || ctx->sp[1].high_degree;
+    if (high && ctx->method != MDET_METHOD_SM_CHAIN)
+        throw Status(MDET_EDEGREE, "excitation degree above " + std::to_string(MDET_MAX_DEGREE) +
+                                       ": evaluate with MDET_METHOD_SM_CHAIN (mdet_set_method)");
+    if (high && max_degree_dev)
+        throw Status(MDET_EINVAL, "per-walker degree limits need excitation degrees <= " +
+                                      std::to_string(MDET_MAX_DEGREE));
     ensure_work(ctx, n_walk);
     ensure_chain(ctx, n_walk);
     KernelArgs a{};
@@ -598,6 +618,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
                 acc += (int32_t)ctx->sp[s].n_by_degree[k];
                 d.deg_end[k] = acc;
             }
+            d.deg_end[MDET_MAX_DEGREE] += (int32_t)ctx->sp[s].n_above;  // the last bucket: all the rest
         }
         d.occ0 = ctx->sp[s].d_occ0.as<int32_t>();
         d.desc = ctx->sp[s].d_desc.as<DetDesc>();
@@ -863,8 +884,9 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
         std::vector<int32_t> rdeg((size_t)U * DD), cdeg((size_t)V * DD);
         {
             std::vector<int> deg_up(U), deg_dn(V);
-            for (int64_t e = 0; e < U; ++e) deg_up[e] = sp[0].desc[e].s;
-            for (int64_t e = 0; e < V; ++e) deg_dn[e] = sp[1].desc[e].s;
+            // degrees above MDET_MAX_DEGREE (chain method only) share the last bucket
+            for (int64_t e = 0; e < U; ++e) deg_up[e] = std::min<int>(sp[0].desc[e].s, MDET_MAX_DEGREE);
+            for (int64_t e = 0; e < V; ++e) deg_dn[e] = std::min<int>(sp[1].desc[e].s, MDET_MAX_DEGREE);
             for (int64_t i = 0; i < U; ++i)
                 for (int d = 0; d < DD; ++d) {
                     int32_t k = rptr[i];
@@ -923,6 +945,8 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->sp[s].pub_of.swap(sp[s].pub_of);
             ctx->sp[s].desc.swap(sp[s].desc);
             for (int k = 0; k <= MDET_MAX_DEGREE; ++k) ctx->sp[s].n_by_degree[k] = sp[s].n_by_degree[k];
+            ctx->sp[s].high_degree = sp[s].high_degree;
+            ctx->sp[s].n_above = sp[s].n_above;
             ctx->sp[s].adj_off.swap(sp[s].adj_off);
             ctx->sp[s].chunk_det.swap(sp[s].chunk_det);
             ctx->sp[s].gptr.swap(sp[s].gptr);

@@ -128,9 +128,11 @@ def test_error_codes():
     dup_d = np.concatenate([wl.det_dn, wl.det_dn[7:8]])
     _expect(-5, lambda: ev.set_expansion(5, 5, dup_u, dup_d, np.append(wl.c, 0.01)))  # EDUPLICATE
     far = encode([[15, 16, 17, 18, 19]], 1)                                    # degree 5 from ref
-    _expect(-10, lambda: ev.set_expansion(5, 5, np.concatenate([wl.det_up, far]),
-                                          np.concatenate([wl.det_dn, wl.det_dn[:1]]),
-                                          np.append(wl.c, 0.001)))            # EDEGREE
+    # accepted (the chain method evaluates it); the degree shows in the counts
+    ev.set_expansion(5, 5, np.concatenate([wl.det_up, far]),
+                     np.concatenate([wl.det_dn, wl.det_dn[:1]]), np.append(wl.c, 0.001))
+    st = ev.stats()
+    assert sum(st.n_by_degree_up) == st.n_uniq_up - 1
     ev.set_expansion(5, 5, wl.det_up, wl.det_dn, wl.c)                         # still usable
     _expect(-9, lambda: ev.eval_raw(1, None, 0, None, None, None, None, None, None))
     _expect(-1, lambda: ev.set_fallback_threshold(-1.0))

@@ -135,3 +135,31 @@ def test_chain_honours_max_degree_and_graphs():
     s3, l3, g3, w3 = gpu_eval(ev, wl.R, max_degree=md)
     ep, eg = scaled_errors(ref, s3, l3, g3)
     assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
+
+
+def test_excitation_degrees_up_to_eight_by_the_chain():
+    """Degrees 1-8 from the reference: the table method refuses the expansion,
+    the chain evaluates it (no degree limit along the sorted list)."""
+    from gen.workloads import make_custom
+    log("[sm] degrees up to 8, 9+8 electrons, 60 orbitals")
+    wl = make_custom(9, 8, 60, 3, 200, 150, (1, 2, 4, 6, 8), 3000, 64, seed=21)
+    direct = oracle.evaluate(wl, max_degree=None, n_threads=16)
+    chain = oracle.sm_evaluate(wl, n_threads=16)
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    with pytest.raises(mdet.MdetError) as ei:
+        gpu_eval(ev, wl.R)
+    assert ei.value.code == -10
+    ev.set_method(mdet.METHOD_SM_CHAIN, 1e-3, 1)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R)
+    ep, eg = scaled_errors(direct, sign, logabs, gl)
+    summary("degree 8, pieces of 1", ep, eg, ws)
+    assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
+    ev.set_method(mdet.METHOD_SM_CHAIN, 1e-3, 1 << 20)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R)
+    cnt = ev.sm_counters()
+    ep, eg = scaled_errors(direct, sign, logabs, gl)
+    cp, cg = scaled_errors(direct, chain.sign, chain.logabs, chain.gl)
+    summary("degree 8, one piece", ep, eg, ws)
+    assert abs(cnt["n_subst"] - chain.n_subst) <= 1e-3 * max(chain.n_subst, 1000)
+    assert ep.max() <= max(FP64_TOL, 10 * cp.max()) and eg.max() <= max(FP64_TOL, 10 * cg.max())
