@@ -55,6 +55,10 @@ class Workload:
     c: np.ndarray            # f64 [n_det]
     R: np.ndarray            # f64 [n_walk][n_up+n_dn][3]
     max_degree: Optional[np.ndarray] = None   # int8 [n_walk] or None
+    # optional separate orbitals of the down electrons (same shapes)
+    pow_abc_dn: Optional[np.ndarray] = None
+    alpha_dn: Optional[np.ndarray] = None
+    coef_dn: Optional[np.ndarray] = None
 
     @property
     def n_elec(self) -> int:
@@ -204,6 +208,15 @@ def make_custom(n_up, n_dn, n_mo, n_prim, n_uniq_up, n_uniq_dn, degrees, n_det,
                     det_up=np.ascontiguousarray(encode(ups, n_int)[ii]),
                     det_dn=np.ascontiguousarray(encode(dns, n_int)[jj]),
                     c=c, R=R, max_degree=md)
+
+
+def with_down_orbitals(wl: Workload, seed: int = 1) -> Workload:
+    """The same workload with a second, independently drawn orbital set for
+    the down electrons (same monomials, other exponents and coefficients)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed))
+    alpha = wl.alpha * np.exp(rng.uniform(-0.3, 0.3, size=wl.alpha.shape))
+    coef = rng.standard_normal(wl.coef.shape)
+    return dataclasses.replace(wl, pow_abc_dn=wl.pow_abc.copy(), alpha_dn=alpha, coef_dn=coef)
 
 
 def make_helium(n_walk: int, seed: int = 0, sigma: float = 0.8) -> Workload:

@@ -102,6 +102,17 @@ mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim,
                                const double *coef);
 
 /*
+ * Separate orbitals for the down electrons (Eq. (1) uses one common set; the
+ * paper notes that two sets are a direct generalisation, Sec. 2): the
+ * matrices of the down determinants take phi_j^dn(r_i).  Same layout and
+ * limits as mdet_init_orbitals, with that call's n_mo and n_prim.  Keeps the
+ * expansion; a later mdet_init_orbitals returns to one common set.
+ * Synchronous (waits for the device).
+ */
+mdet_status mdet_init_orbitals_dn(mdet_ctx *ctx, const int32_t *pow_abc, const double *alpha,
+                                  const double *coef);
+
+/*
  * CI expansion (Eq. (1)) and its one-time pre-processing (Sec. 2.1):
  * encoding check, xor-key sort and duplicate removal of each spin list,
  * binary search of every product, column-major ordering of the sparse C,

@@ -52,15 +52,15 @@ def _load():
         P = ctypes.c_void_p
         lib.orc_eval.restype = ctypes.c_int
         lib.orc_eval.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P, P,
-                                 ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_int64, P, P,
-                                 ctypes.c_int, P, P, P, P, P, ctypes.c_int]
+                                 P, P, P, ctypes.c_int, ctypes.c_int64, P, P, P, ctypes.c_int64,
+                                 P, P, ctypes.c_int, P, P, P, P, P, ctypes.c_int]
         lib.orc_orbitals.restype = None
         lib.orc_orbitals.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P]
         lib.orc_slater.restype = ctypes.c_int
         lib.orc_slater.argtypes = [ctypes.c_int, P, P, P, P, P, P]
         I, L = ctypes.c_int, ctypes.c_int64
         lib.orc_sm_eval.restype = ctypes.c_int
-        lib.orc_sm_eval.argtypes = [I, I, I, I, P, P, P, I, L, P, L, P, L, P, P, P, L, P,
+        lib.orc_sm_eval.argtypes = [I, I, I, I, P, P, P, P, P, P, I, L, P, L, P, L, P, P, P, L, P,
                                     ctypes.c_double, I, P, P, P, P]
         _lib = lib
     return _lib
@@ -70,12 +70,29 @@ def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
 
 
-def orbitals(wl, r):
-    """[5][n_mo] values, grad x,y,z and Laplacian of every orbital at point r."""
+def _orbital_set(wl, spin):
+    """(pow_abc, alpha, coef) of the orbitals of `spin` (the down set if the
+    workload has its own)."""
+    if spin == 1 and getattr(wl, "alpha_dn", None) is not None:
+        return wl.pow_abc_dn, wl.alpha_dn, wl.coef_dn
+    return wl.pow_abc, wl.alpha, wl.coef
+
+
+def _down_arrays(wl):
+    if getattr(wl, "alpha_dn", None) is None:
+        return None, None, None
+    return (np.ascontiguousarray(wl.pow_abc_dn, dtype=np.int32),
+            np.ascontiguousarray(wl.alpha_dn, dtype=np.float64),
+            np.ascontiguousarray(wl.coef_dn, dtype=np.float64))
+
+
+def orbitals(wl, r, spin=0):
+    """[5][n_mo] values, grad x,y,z and Laplacian of every orbital of `spin` at point r."""
     lib = _load()
-    pw = np.ascontiguousarray(wl.pow_abc, dtype=np.int32)
-    al = np.ascontiguousarray(wl.alpha, dtype=np.float64)
-    cf = np.ascontiguousarray(wl.coef, dtype=np.float64)
+    pw0, al0, cf0 = _orbital_set(wl, spin)
+    pw = np.ascontiguousarray(pw0, dtype=np.int32)
+    al = np.ascontiguousarray(al0, dtype=np.float64)
+    cf = np.ascontiguousarray(cf0, dtype=np.float64)
     r = np.ascontiguousarray(r, dtype=np.float64)
     out = np.zeros((5, wl.n_mo))
     lib.orc_orbitals(wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf), _p(r), _p(out))
@@ -127,7 +144,9 @@ def evaluate(wl, R=None, max_degree="auto", mode=0, n_threads=0, c=None,
     gl = np.zeros((W, N, 4))
     rs_psi = np.zeros(W)
     rs_gl = np.zeros((W, N, 4))
-    rc = lib.orc_eval(wl.n_up, wl.n_dn, wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf), wl.n_int,
+    pwd, ald, cfd = _down_arrays(wl)
+    rc = lib.orc_eval(wl.n_up, wl.n_dn, wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf), _p(pwd),
+                      _p(ald), _p(cfd), wl.n_int,
                       int(c.shape[0]), _p(du), _p(dd), _p(c), W, _p(R), _p(md), int(mode),
                       _p(sign), _p(logabs), _p(gl), _p(rs_psi), _p(rs_gl), int(n_threads))
     if rc != 0:
@@ -191,8 +210,9 @@ def sm_evaluate(wl, R=None, threshold=1e-3, n_threads=0, det_up=None, det_dn=Non
     logabs = np.zeros(W)
     gl = np.zeros((W, N, 4))
     stats = np.zeros(3, dtype=np.int64)
-    rc = lib.orc_sm_eval(wl.n_up, wl.n_dn, wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf),
-                         uu.shape[1], uu.shape[0], _p(uu), ud.shape[0], _p(ud), val.shape[0],
+    pwd, ald, cfd = _down_arrays(wl)
+    rc = lib.orc_sm_eval(wl.n_up, wl.n_dn, wl.n_mo, wl.n_prim, _p(pw), _p(al), _p(cf), _p(pwd),
+                         _p(ald), _p(cfd), uu.shape[1], uu.shape[0], _p(uu), ud.shape[0], _p(ud), val.shape[0],
                          _p(ri), _p(cj), _p(val), W, _p(R), float(threshold), int(n_threads),
                          _p(sign), _p(logabs), _p(gl), _p(stats))
     if rc != 0:

@@ -57,7 +57,7 @@ def det_and_grad(S, G):
 def psi_brute(wl, Rw):
     """Psi and grad~Psi (unnormalised, FP64, no scaling) by Eq. (1) with Leibniz."""
     N = wl.n_up + wl.n_dn
-    orb = np.array([_orbitals(wl, Rw[e]) for e in range(N)])  # [N][5][M]
+    orb = np.array([_orbitals(wl, Rw[e], spin=int(e >= wl.n_up)) for e in range(N)])  # [N][5][M]
     cache = {}
 
     def spin_det(words, e0, n):

@@ -279,7 +279,8 @@ static inline double nval(const nsum *a) { return a->s + a->c; }
  * Returns 0 on success, <0 on bad input.
  */
 int orc_eval(int n_up, int n_dn, int n_mo, int n_prim, const int32_t *pw,
-             const double *alpha, const double *coef, int n_int, int64_t n_det,
+             const double *alpha, const double *coef, const int32_t *pw_dn,
+             const double *alpha_dn, const double *coef_dn, int n_int, int64_t n_det,
              const uint64_t *det_up, const uint64_t *det_dn, const double *c,
              int64_t n_walk, const double *R, const int8_t *max_degree, int mode,
              double *sign_out, double *logabs_out, double *gl_out,
@@ -353,8 +354,13 @@ int orc_eval(int n_up, int n_dn, int n_mo, int n_prim, const int32_t *pw,
 #pragma omp for schedule(dynamic, 1)
         for (int64_t w = 0; w < n_walk; ++w) {
             const double *Rw = R + w * N * 3;
-            for (int e = 0; e < N; ++e)
-                orc_orbitals(n_mo, n_prim, pw, alpha, coef, Rw + 3 * e, orb + e * 5 * n_mo);
+            for (int e = 0; e < N; ++e) {
+                /* Eq. (1): S^sigma_k[i][j] = phi^sigma_j(r_i); one common set unless the
+                 * down electrons have their own */
+                const int dn = e >= n_up && alpha_dn;
+                orc_orbitals(n_mo, n_prim, dn ? pw_dn : pw, dn ? alpha_dn : alpha,
+                             dn ? coef_dn : coef, Rw + 3 * e, orb + e * 5 * n_mo);
+            }
             /* spin determinants */
             for (int spin = 0; spin < 2; ++spin) {
                 int n = spin == 0 ? n_up : n_dn;

@@ -222,7 +222,8 @@ static void chain(int n, int M, const double *P, const int *kx, int64_t U, const
  * orc_eval: sign [W], logabs [W], gl [W][N][4]; stats [3] summed over walkers.
  */
 int orc_sm_eval(int n_up, int n_dn, int n_mo, int n_prim, const int32_t *pw, const double *alpha,
-                const double *coef, int n_int, int64_t U, const uint64_t *uniq_up, int64_t V,
+                const double *coef, const int32_t *pw_dn, const double *alpha_dn,
+                const double *coef_dn, int n_int, int64_t U, const uint64_t *uniq_up, int64_t V,
                 const uint64_t *uniq_dn, int64_t nnz, const int32_t *row_i, const int32_t *col_j,
                 const double *val, int64_t W, const double *R, double threshold, int n_threads,
                 double *sign, double *logabs, double *gl, int64_t *stats)
@@ -252,9 +253,12 @@ int orc_sm_eval(int n_up, int n_dn, int n_mo, int n_prim, const int32_t *pw, con
         double *rtd = malloc(sizeof(double) * V * 4 * (n_dn > 0 ? n_dn : 1));
 #pragma omp for schedule(dynamic)
         for (int64_t w = 0; w < W; ++w) {
-            for (int e = 0; e < N; ++e)
-                orc_orbitals(n_mo, n_prim, pw, alpha, coef, R + (w * N + e) * 3,
+            for (int e = 0; e < N; ++e) {
+                const int dn = e >= n_up && alpha_dn;  /* the down electrons' own set, if any */
+                orc_orbitals(n_mo, n_prim, dn ? pw_dn : pw, dn ? alpha_dn : alpha,
+                             dn ? coef_dn : coef, R + (w * N + e) * 3,
                              phi + (size_t)e * 5 * M);  /* [e][5][M] */
+            }
             /* per spin: power-of-two column scaling, layout [q][e][m] */
             for (int s = 0; s < 2; ++s) {
                 const int n = s ? n_dn : n_up, e0 = s ? n_up : 0;

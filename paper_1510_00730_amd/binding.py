@@ -32,7 +32,7 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step", "mdet_set_launch_config",
             "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune",
             "mdet_norm_truncation", "mdet_set_method", "mdet_get_sm_counters",
-            "mdet_set_jastrow", "mdet_dmc_step"]
+            "mdet_set_jastrow", "mdet_dmc_step", "mdet_init_orbitals_dn"]
 METHOD_TABLE, METHOD_SM_CHAIN = 0, 1
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
 RNG_UNIFORM, RNG_NORMAL = 0, 1
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_set_method": (I32, [P, I32, D, I32]),
         "mdet_get_sm_counters": (I32, [P, P]),
         "mdet_set_jastrow": (I32, [P, I32, D, D, D]),
+        "mdet_init_orbitals_dn": (I32, [P, P, P, P]),
         "mdet_dmc_step": (I32, [P, I64, D, D, D, I32, P, P, P, P, P, P, P, P, D, P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -159,6 +160,13 @@ class Evaluator:
         self._check(_LIB.mdet_init_orbitals(self._h, n_mo, n_prim, _ptr(pw), _ptr(al), _ptr(cf)))
         self.n_mo = n_mo
 
+    def init_orbitals_dn(self, pow_abc, alpha, coef):
+        """Separate orbitals for the down electrons (same shapes as init_orbitals)."""
+        pw = np.ascontiguousarray(pow_abc, dtype=np.int32)
+        al = np.ascontiguousarray(alpha, dtype=np.float64)
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        self._check(_LIB.mdet_init_orbitals_dn(self._h, _ptr(pw), _ptr(al), _ptr(cf)))
+
     def set_expansion(self, n_up, n_dn, det_up, det_dn, c, n_int=None):
         du = np.ascontiguousarray(det_up, dtype=np.uint64)
         dd = np.ascontiguousarray(det_dn, dtype=np.uint64)
@@ -173,6 +181,8 @@ class Evaluator:
 
     def load_workload(self, wl):
         self.init_orbitals(wl.pow_abc, wl.alpha, wl.coef)
+        if getattr(wl, "alpha_dn", None) is not None:
+            self.init_orbitals_dn(wl.pow_abc_dn, wl.alpha_dn, wl.coef_dn)
         self.set_expansion(wl.n_up, wl.n_dn, wl.det_up, wl.det_dn, wl.c, wl.n_int)
 
     def set_fallback_threshold(self, kappa_max: float):

@@ -101,6 +101,10 @@ struct mdet_ctx {
     int n_mo = 0, n_prim = 0;
     std::vector<Prim> prim;
     DevBuf d_prim;
+    // optional separate orbitals of the down electrons (same n_mo, n_prim)
+    bool two_sets = false;
+    std::vector<Prim> prim_dn;
+    DevBuf d_prim_dn;
     // expansion
     bool have_exp = false;
     int n_up = 0, n_dn = 0, n_int = 0;
@@ -238,7 +242,7 @@ struct mdet_ctx {
         return t;
     }
     int64_t exp_bytes() const {
-        int64_t t = (int64_t)d_prim.bytes;
+        int64_t t = (int64_t)(d_prim.bytes + d_prim_dn.bytes);
         for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rseg, &d_cptr, &d_crow,
                                 &d_cval, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             t += (int64_t)b->bytes;
@@ -606,6 +610,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.nmax = std::max(ctx->n_up, ctx->n_dn);
     a.kappa_max = ctx->kappa_max;
     a.prim = ctx->d_prim.as<Prim>();
+    a.prim_dn = ctx->two_sets ? ctx->d_prim_dn.as<Prim>() : a.prim;
     for (int s = 0; s < 2; ++s) {
         SpinDev &d = a.sp[s];
         d.n = ctx->sp[s].n;
@@ -750,6 +755,7 @@ void mdet_destroy(mdet_ctx *ctx) {
     }
     ctx->drop_expansion();
     ctx->d_prim.release();
+    ctx->d_prim_dn.release();
     ctx->drop_graphs();
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
     ctx->drop_vmc();
@@ -759,33 +765,60 @@ void mdet_destroy(mdet_ctx *ctx) {
 
 const char *mdet_last_error(const mdet_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+namespace {
+std::vector<Prim> pack_primitives(int32_t n_mo, int32_t n_prim, const int32_t *pow_abc,
+                                  const double *alpha, const double *coef) {
+    require(pow_abc && alpha && coef, MDET_EINVAL, "null orbital array");
+    std::vector<Prim> pr((size_t)n_mo * n_prim);
+    for (int64_t t = 0; t < (int64_t)n_mo * n_prim; ++t) {
+        Prim &p = pr[t];
+        p.alpha = alpha[t];
+        p.coef = coef[t];
+        p.a = pow_abc[3 * t];
+        p.b = pow_abc[3 * t + 1];
+        p.c = pow_abc[3 * t + 2];
+        p.pad = 0;
+        require(p.a >= 0 && p.a <= 4 && p.b >= 0 && p.b <= 4 && p.c >= 0 && p.c <= 4,
+                MDET_EINVAL, "monomial power outside 0..4");
+        require(std::isfinite(p.alpha) && p.alpha > 0.0 && std::isfinite(p.coef), MDET_EINVAL,
+                "exponents must be finite and positive, coefficients finite");
+    }
+    return pr;
+}
+}  // namespace
+
 mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim, const int32_t *pow_abc,
                                const double *alpha, const double *coef) {
     return guarded(ctx, [&] {
-        require(pow_abc && alpha && coef, MDET_EINVAL, "null orbital array");
         require(n_mo >= 1 && n_mo <= MDET_MAX_MO, MDET_EDIM, "n_mo out of range");
         require(n_prim >= 1 && n_prim <= 16, MDET_EDIM, "n_prim out of range");
-        std::vector<Prim> pr((size_t)n_mo * n_prim);
-        for (int64_t t = 0; t < (int64_t)n_mo * n_prim; ++t) {
-            Prim &p = pr[t];
-            p.alpha = alpha[t];
-            p.coef = coef[t];
-            p.a = pow_abc[3 * t];
-            p.b = pow_abc[3 * t + 1];
-            p.c = pow_abc[3 * t + 2];
-            p.pad = 0;
-            require(p.a >= 0 && p.a <= 4 && p.b >= 0 && p.b <= 4 && p.c >= 0 && p.c <= 4,
-                    MDET_EINVAL, "monomial power outside 0..4");
-            require(std::isfinite(p.alpha) && p.alpha > 0.0 && std::isfinite(p.coef), MDET_EINVAL,
-                    "exponents must be finite and positive, coefficients finite");
-        }
+        std::vector<Prim> pr = pack_primitives(n_mo, n_prim, pow_abc, alpha, coef);
         if (!ctx->host_only) HIP_OK(hipSetDevice(ctx->device));
         ctx->drop_expansion();
         if (!ctx->host_only) ctx->d_prim.upload(pr);
         ctx->prim.swap(pr);
+        ctx->two_sets = false;
+        ctx->prim_dn.clear();
+        ctx->d_prim_dn.release();
         ctx->n_mo = n_mo;
         ctx->n_prim = n_prim;
         ctx->have_orb = true;
+    });
+}
+
+mdet_status mdet_init_orbitals_dn(mdet_ctx *ctx, const int32_t *pow_abc, const double *alpha,
+                                  const double *coef) {
+    return guarded(ctx, [&] {
+        require(ctx->have_orb, MDET_ESTATE, "mdet_init_orbitals must come first");
+        std::vector<Prim> pr = pack_primitives(ctx->n_mo, ctx->n_prim, pow_abc, alpha, coef);
+        if (!ctx->host_only) {
+            HIP_OK(hipSetDevice(ctx->device));
+            HIP_OK(hipDeviceSynchronize());  // no evaluation may still read the old set
+            ctx->d_prim_dn.upload(pr);
+        }
+        ctx->prim_dn.swap(pr);
+        ctx->two_sets = true;
+        ctx->drop_graphs();
     });
 }
 

@@ -143,7 +143,8 @@ constexpr int kPsiParts = 16;
 struct KernelArgs {
     int32_t n_up, n_dn, N, M, P, nmax;
     double kappa_max;
-    const Prim *prim;         // [M][P]
+    const Prim *prim;         // [M][P] orbitals of the up electrons (and of all, if one set)
+    const Prim *prim_dn;      // [M][P] orbitals of the down electrons (== prim for one set)
     SpinDev sp[2];
     SparseDev C;
     Work wk;

@@ -451,19 +451,23 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     int *slot = emax + 2 * M;         // [2][M] reference slot of orbital m, or -1
     double *pw = (double *)(slot + 2 * M);  // [N][3][kPowLd] coordinate powers
     double *r2s = pw + N * 3 * kPowLd;      // [N] |r|^2
-    // the primitives, staged as [p][m] arrays when they fit (else read from
-    // HBM): consecutive orbitals in consecutive LDS words
+    // the primitives (one set, or one per spin), staged as [set][p][m] arrays
+    // when they fit (else read from HBM): consecutive orbitals in consecutive
+    // LDS words
     const int MP = M * a.P;
-    const bool stage_prim = (size_t)MP * kPrimLdsBytes <= kPrimLdsMax;
-    double *p_al = r2s + N, *p_cf = p_al + MP;
-    int *p_abc = (int *)(p_cf + MP);
+    const int nsets = a.prim_dn != a.prim ? 2 : 1;
+    const bool stage_prim = (size_t)nsets * MP * kPrimLdsBytes <= kPrimLdsMax;
+    double *p_al = r2s + N, *p_cf = p_al + nsets * MP;
+    int *p_abc = (int *)(p_cf + nsets * MP);
     if (stage_prim)
-        for (int i = tid; i < MP; i += kBlock) {
-            const int m = i / a.P, p = i - m * a.P;
-            const Prim q = a.prim[i];
-            p_al[p * M + m] = q.alpha;
-            p_cf[p * M + m] = q.coef;
-            p_abc[p * M + m] = q.a | (q.b << 8) | (q.c << 16);
+        for (int i = tid; i < nsets * MP; i += kBlock) {
+            const int set = i >= MP, j = i - set * MP;
+            const int m = j / a.P, p = j - m * a.P;
+            const Prim q = (set ? a.prim_dn : a.prim)[j];
+            const int o = set * MP + p * M + m;
+            p_al[o] = q.alpha;
+            p_cf[o] = q.coef;
+            p_abc[o] = q.a | (q.b << 8) | (q.c << 16);
         }
 
     if (w == 0 && tid == 0) a.wk.dcount[0] = 0;  // fallback list, filled by k_ratios
@@ -497,10 +501,12 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     // orbitals and derivatives, written once (unscaled)
     for (int idx = tid; idx < N * M; idx += kBlock) {
         const int e = idx / M, m = idx - e * M;
+        const int set = (nsets == 2 && e >= nup) ? 1 : 0;  // the down electrons' own orbitals
         double o[5];
-        if (stage_prim) orbital5_tab<true>(nullptr, p_al, p_cf, p_abc, a.P, M, m,
-                                           pw + e * 3 * kPowLd, r2s[e], o);
-        else orbital5_tab<false>(a.prim, nullptr, nullptr, nullptr, a.P, M, m,
+        if (stage_prim) orbital5_tab<true>(nullptr, p_al + set * MP, p_cf + set * MP,
+                                           p_abc + set * MP, a.P, M, m, pw + e * 3 * kPowLd,
+                                           r2s[e], o);
+        else orbital5_tab<false>(set ? a.prim_dn : a.prim, nullptr, nullptr, nullptr, a.P, M, m,
                                  pw + e * 3 * kPowLd, r2s[e], o);
         double *dst = phig + (size_t)e * 5 * M + m;
 #pragma unroll
@@ -1674,7 +1680,7 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], st);
     };
     mark(0, false);
-    const size_t prim_bytes = (size_t)M * a.P * kPrimLdsBytes;
+    const size_t prim_bytes = (size_t)(a.prim_dn != a.prim ? 2 : 1) * M * a.P * kPrimLdsBytes;
     const size_t lds_ref = sizeof(double) * (14 * (size_t)n * n + 2 * (2 * kMaxN + 2) +
                                              (size_t)a.N * (3 * kPowLd + 1)) +
                            sizeof(int) * 4 * (size_t)M + (prim_bytes <= kPrimLdsMax ? prim_bytes : 0);

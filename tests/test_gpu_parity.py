@@ -193,6 +193,24 @@ def test_fp64_parity_many_words(n_mo):
         assert ep.max() <= tol and eg.max() <= tol
 
 
+def test_parity_with_separate_down_orbitals():
+    """Down electrons with their own orbital set, table method and chain."""
+    from gen.workloads import with_down_orbitals
+    log("[parity] config 2 with a separate down-electron orbital set")
+    wl = with_down_orbitals(workload(2))
+    ev = evaluator(wl)
+    ref = oracle.evaluate(wl, n_threads=16)
+    for prec, tol in ((mdet.MDET_FP64, FP64_TOL), (mdet.MDET_MIXED, MIXED_TOL)):
+        sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=prec)
+        ep, eg = scaled_errors(ref, sign, logabs, gl)
+        summary(f"two sets precision {prec}", ep, eg, ws)
+        assert ep.max() <= tol and eg.max() <= tol
+    ev.set_method(mdet.METHOD_SM_CHAIN, 1e-3, 1)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R)
+    ep, eg = scaled_errors(ref, sign, logabs, gl)
+    assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
+
+
 def test_indexing_on_device_context_matches_oracle():
     from oracle import preprocess as pp
     wl = workload(3)

@@ -24,17 +24,26 @@ MUTATIONS = {
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("name", sorted(MUTATIONS))
+@pytest.mark.parametrize("name", ["unmutated_control"] + sorted(MUTATIONS))
 def test_pins_catch_mutation(name, tmp_path):
-    old, new = MUTATIONS[name]
+    """The control build (no change) must pass the pins through the same
+    harness, so a failure of a mutant is the pins' doing."""
     src = open(SRC).read()
-    assert src.count(old) == 1, name
+    if name != "unmutated_control":
+        old, new = MUTATIONS[name]
+        assert src.count(old) == 1, name
+        src = src.replace(old, new)
     mut_c = tmp_path / "oracle_mut.c"
-    mut_c.write_text(src.replace(old, new))
+    mut_c.write_text(src)
     so = tmp_path / "liboracle_mut.so"
-    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", str(mut_c), "-o", str(so), "-lm"])
+    chain_c = os.path.join(ROOT, "oracle", "sm_chain.c")  # the rest of the oracle library
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", str(mut_c), chain_c,
+                           "-o", str(so), "-lm"])
     env = dict(os.environ, MDET_ORACLE_LIB_OVERRIDE=str(so))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, f"mutation {name} survived the pins:\n{r.stdout[-2000:]}"
+    if name == "unmutated_control":
+        assert r.returncode == 0, r.stdout[-2000:]
+    else:
+        assert r.returncode != 0, f"mutation {name} survived the pins:\n{r.stdout[-2000:]}"
