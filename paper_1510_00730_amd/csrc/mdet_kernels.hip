@@ -1127,6 +1127,11 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
 namespace {
 
 constexpr int kDirectBlock = 256;
+// derivative sums of the direct-LU fallback: per wave, the 64 lanes'
+// contributions of kEHalf electrons are staged in LDS (row pitch kWredLd)
+// and added column by column
+constexpr int kEHalf = 5;
+constexpr int kWredLd = 4 * kEHalf + 1;
 
 // LU with partial pivoting of a[K][K] in place; with PERM, perm[i] = original
 // row of row i and the multipliers are kept below the diagonal (without PERM
@@ -1265,7 +1270,7 @@ template <int K>
 __device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, int w, const SpinDev &S,
                                   const int *occ0, const double *P0, const double *Gs,
                                   const double *Gg, const int *Ex, int d0, int d1,
-                                  double *red) {
+                                  double *red, double *wr) {
     const int M = a.M, n = S.n;
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const int Kx = a.wk.K[(size_t)w * 2 + sp];
@@ -1291,8 +1296,10 @@ __device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, i
         const double coef = valid ? wt * ldexp((double)D.eps * mant, rexp - Kx) : 0.0;
 #pragma unroll
         for (int i = 0; i < K; ++i) A[i][i] = 1.0 / A[i][i];  // U's diagonal, inverted
+        for (int e0 = 0; e0 < n; e0 += kEHalf) {
+        const int e1 = min(n, e0 + kEHalf);
 #pragma unroll 1
-        for (int e = 0; e < n; ++e) {
+        for (int e = e0; e < e1; ++e) {
             // column e of S_d^-1
             double x[K];
 #pragma unroll
@@ -1321,9 +1328,17 @@ __device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, i
                     for (int c = 0; c < K; ++c)
                         if (c < n) s += x[c] * (G[occ[c]] * pow2(-Ex[occ[c]]));
                 }
-                const double v = wave_sum(valid ? coef * s : 0.0);
-                if (lane == 0) red[wave * 4 * K + e * 4 + q] += v;
+                wr[lane * kWredLd + (e - e0) * 4 + q] = valid ? coef * s : 0.0;
             }
+        }
+        // the wave's sums of this group of electrons: lane t adds column t over the lanes
+        wave_lds_sync();
+        if (lane < (e1 - e0) * 4) {
+            double t = 0.0;
+            for (int l = 0; l < 64; ++l) t += wr[l * kWredLd + lane];
+            red[wave * 4 * K + e0 * 4 + lane] += t;
+        }
+        wave_lds_sync();
         }
     }
 }
@@ -1421,7 +1436,8 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a) {
     double *P0 = lds;                                  // [NT][M] scaled values
     double *G = stage_g ? P0 + NT * M : nullptr;       // [4][NT][M] scaled derivatives
     double *red = P0 + (stage_g ? 5 : 1) * NT * M;     // [kDirectBlock / 64][NT * 4]
-    int *Ex = (int *)(red + (kDirectBlock / 64) * NT * 4);  // [M]
+    double *wred = red + (kDirectBlock / 64) * NT * 4;  // [kDirectBlock / 64][64][kWredLd]
+    int *Ex = (int *)(wred + (kDirectBlock / 64) * 64 * kWredLd);  // [M]
     int *occ0 = Ex + M;                                // [NT]
     const int nitems = a.wk.dcount[0] * split;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -1444,10 +1460,11 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a) {
         if (NT > 1 && n == NT - 1) {
             K = NT > 1 ? NT - 1 : 1;
             direct_deriv_item<(NT > 1 ? NT - 1 : 1)>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1,
-                                                      red);
+                                                      red, wred + (tid >> 6) * 64 * kWredLd);
         } else {
             K = NT;  // n <= NT
-            direct_deriv_item<NT>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1, red);
+            direct_deriv_item<NT>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1, red,
+                                  wred + (tid >> 6) * 64 * kWredLd);
         }
         __syncthreads();
         for (int i = tid; i < n * 4; i += kDirectBlock) {
@@ -1591,7 +1608,7 @@ void launch_direct(const KernelArgs &a, hipStream_t st, bool deriv) {
     const unsigned grid = (unsigned)std::min<int64_t>(2 * a.W * a.direct_split, 1024);
     if (deriv) {
         const size_t lds = sizeof(double) * ((a.direct_stage_grad ? 5 : 1) * (size_t)NT * M +
-                                             (kDirectBlock / 64) * NT * 4) +
+                                             (kDirectBlock / 64) * (NT * 4 + 64 * kWredLd)) +
                            sizeof(int) * (M + NT);
         k_direct_deriv_t<NT><<<dim3(grid), dim3(kDirectBlock), lds, st>>>(a);
     } else {
