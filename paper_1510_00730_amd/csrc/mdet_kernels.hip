@@ -1349,12 +1349,32 @@ __device__ void stage_orbitals(const KernelArgs &a, int w, int e0, int n, const 
                                double *P0, double *G) {
     const int M = a.M;
     const double *phig = a.wk.phi + ((size_t)w * a.N + e0) * 5 * M;
+    // source index j over the planes taken: [e][q][m] with q < nq (contiguous
+    // when all five are taken); eight loads in flight per thread before the stores
     const int nq = G ? 5 : 1;
-    for (int i = threadIdx.x; i < nq * n * M; i += blockDim.x) {
-        const int q = i / (n * M), r = i - q * n * M, e = r / M, m = r - e * M;
-        const double v = phig[(size_t)e * 5 * M + (size_t)q * M + m] * pow2(-Ex[m]);
-        if (q == 0) P0[r] = v;
-        else G[i - n * M] = v;
+    const int tot = n * nq * M;
+    constexpr int kU = 8;
+    for (int base = threadIdx.x; base < tot; base += kU * blockDim.x) {
+        double v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int j = base + u * (int)blockDim.x;
+            v[u] = 0.0;
+            if (j < tot) {
+                const int e = j / (nq * M), r = j - e * nq * M;
+                v[u] = phig[(size_t)e * 5 * M + r];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int j = base + u * (int)blockDim.x;
+            if (j < tot) {
+                const int e = j / (nq * M), r = j - e * nq * M, q = r / M, m = r - q * M;
+                const double x = v[u] * pow2(-Ex[m]);
+                if (q == 0) P0[e * M + m] = x;
+                else G[((q - 1) * n + e) * M + m] = x;
+            }
+        }
     }
 }
 
