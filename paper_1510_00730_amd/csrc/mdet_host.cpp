@@ -722,6 +722,28 @@ void ensure_vmc(mdet_ctx *c, int64_t W, int H) {
 
 }  // namespace
 
+namespace {
+std::vector<Prim> pack_primitives(int32_t n_mo, int32_t n_prim, const int32_t *pow_abc,
+                                  const double *alpha, const double *coef) {
+    require(pow_abc && alpha && coef, MDET_EINVAL, "null orbital array");
+    std::vector<Prim> pr((size_t)n_mo * n_prim);
+    for (int64_t t = 0; t < (int64_t)n_mo * n_prim; ++t) {
+        Prim &p = pr[t];
+        p.alpha = alpha[t];
+        p.coef = coef[t];
+        p.a = pow_abc[3 * t];
+        p.b = pow_abc[3 * t + 1];
+        p.c = pow_abc[3 * t + 2];
+        p.pad = 0;
+        require(p.a >= 0 && p.a <= 4 && p.b >= 0 && p.b <= 4 && p.c >= 0 && p.c <= 4,
+                MDET_EINVAL, "monomial power outside 0..4");
+        require(std::isfinite(p.alpha) && p.alpha > 0.0 && std::isfinite(p.coef), MDET_EINVAL,
+                "exponents must be finite and positive, coefficients finite");
+    }
+    return pr;
+}
+}  // namespace
+
 extern "C" {
 
 
@@ -765,27 +787,6 @@ void mdet_destroy(mdet_ctx *ctx) {
 
 const char *mdet_last_error(const mdet_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-namespace {
-std::vector<Prim> pack_primitives(int32_t n_mo, int32_t n_prim, const int32_t *pow_abc,
-                                  const double *alpha, const double *coef) {
-    require(pow_abc && alpha && coef, MDET_EINVAL, "null orbital array");
-    std::vector<Prim> pr((size_t)n_mo * n_prim);
-    for (int64_t t = 0; t < (int64_t)n_mo * n_prim; ++t) {
-        Prim &p = pr[t];
-        p.alpha = alpha[t];
-        p.coef = coef[t];
-        p.a = pow_abc[3 * t];
-        p.b = pow_abc[3 * t + 1];
-        p.c = pow_abc[3 * t + 2];
-        p.pad = 0;
-        require(p.a >= 0 && p.a <= 4 && p.b >= 0 && p.b <= 4 && p.c >= 0 && p.c <= 4,
-                MDET_EINVAL, "monomial power outside 0..4");
-        require(std::isfinite(p.alpha) && p.alpha > 0.0 && std::isfinite(p.coef), MDET_EINVAL,
-                "exponents must be finite and positive, coefficients finite");
-    }
-    return pr;
-}
-}  // namespace
 
 mdet_status mdet_init_orbitals(mdet_ctx *ctx, int32_t n_mo, int32_t n_prim, const int32_t *pow_abc,
                                const double *alpha, const double *coef) {
