@@ -265,6 +265,13 @@ mdet_status mdet_get_stats(const mdet_ctx *ctx, mdet_stats *out);
 mdet_status mdet_set_profiling(mdet_ctx *ctx, int32_t enable);
 
 /*
+ * As mdet_set_profiling, timing only the kernels whose bit is set in mask
+ * (bit k = kernel k of mdet_get_kernel_times); mask 0 turns timing off.
+ * Fewer events per call leave less recording work on the stream.
+ */
+mdet_status mdet_set_profiling_mask(mdet_ctx *ctx, uint32_t mask);
+
+/*
  * Accumulated kernel times (milliseconds, summed over the profiled calls,
  * host arrays of `capacity` entries, each nullable), the kernel names
  * (static strings) and counts.  Waits for the last profiled call.

@@ -32,7 +32,8 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_mlp_backward", "mdet_mlp_adam", "mdet_mlp_train_step", "mdet_set_launch_config",
             "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune",
             "mdet_norm_truncation", "mdet_set_method", "mdet_get_sm_counters",
-            "mdet_set_jastrow", "mdet_dmc_step", "mdet_init_orbitals_dn"]
+            "mdet_set_jastrow", "mdet_dmc_step", "mdet_init_orbitals_dn",
+            "mdet_set_profiling_mask"]
 METHOD_TABLE, METHOD_SM_CHAIN = 0, 1
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
 RNG_UNIFORM, RNG_NORMAL = 0, 1
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_get_sm_counters": (I32, [P, P]),
         "mdet_set_jastrow": (I32, [P, I32, D, D, D]),
         "mdet_init_orbitals_dn": (I32, [P, P, P, P]),
+        "mdet_set_profiling_mask": (I32, [P, ctypes.c_uint32]),
         "mdet_dmc_step": (I32, [P, I64, D, D, D, I32, P, P, P, P, P, P, P, P, D, P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -221,8 +223,17 @@ class Evaluator:
         out["ref_up"], out["ref_dn"] = ru.value, rd.value
         return out
 
-    def set_profiling(self, enable: bool):
-        self._check(_LIB.mdet_set_profiling(self._h, 1 if enable else 0))
+    def set_profiling(self, enable: bool, kernels=None):
+        """Per-kernel HIP-event timing of later evaluations: every kernel, or
+        only those named in `kernels` (names as kernel_times reports them)."""
+        if not enable or kernels is None:
+            self._check(_LIB.mdet_set_profiling(self._h, 1 if enable else 0))
+            return
+        order = list(self.kernel_times()[0])
+        mask = 0
+        for name in kernels:
+            mask |= 1 << order.index(name)
+        self._check(_LIB.mdet_set_profiling_mask(self._h, ctypes.c_uint32(mask)))
 
     def kernel_times(self):
         """{kernel name: total ms} over the profiled calls, and the call count."""

@@ -150,6 +150,7 @@ struct mdet_ctx {
     static constexpr int kRing = 64;
     static constexpr int kSetEvents = 2 * kNumKernels;
     bool profiling = false;
+    uint32_t prof_user_mask = 0xffffffffu;  // kernels to time (mdet_set_profiling_mask)
     std::vector<hipEvent_t> prof_ev;  // [kRing][kSetEvents]
     uint32_t prof_mask[kRing] = {0};  // kernel slots recorded in each set
     int prof_head = 0, prof_pending = 0;
@@ -669,7 +670,8 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.logabs_out = logabs_dev;
     a.gl_out = gl_dev;
     a.wstatus = wstatus_dev;
-    hipEvent_t *ev = ctx->profiling ? ctx->next_event_set(kernels_of_method(a.method)) : nullptr;
+    a.ev_mask = kernels_of_method(a.method) & ctx->prof_user_mask;
+    hipEvent_t *ev = ctx->profiling ? ctx->next_event_set(a.ev_mask) : nullptr;
     HIP_OK(launch_eval(a, st, ev));
     if (ctx->jastrow_on)
         launch_jastrow(n_walk, a.N, a.n_up, ctx->jastrow, R_dev, logabs_dev, gl_dev, st);
@@ -1109,9 +1111,16 @@ mdet_status mdet_set_profiling(mdet_ctx *ctx, int32_t enable) {
             for (auto &e : ctx->prof_ev) HIP_OK(hipEventCreate(&e));
         }
         ctx->profiling = enable != 0;
+        ctx->prof_user_mask = 0xffffffffu;
         for (double &m : ctx->prof_ms) m = 0.0;
         ctx->prof_calls = 0;
     });
+}
+
+mdet_status mdet_set_profiling_mask(mdet_ctx *ctx, uint32_t mask) {
+    const mdet_status st = mdet_set_profiling(ctx, mask != 0);
+    if (st == MDET_OK) ctx->prof_user_mask = mask ? mask : 0xffffffffu;
+    return st;
 }
 
 mdet_status mdet_get_kernel_times(mdet_ctx *ctx, int32_t capacity, double *ms_total,

@@ -159,6 +159,7 @@ struct KernelArgs {
     int32_t method;           // MDET_METHOD_TABLE or MDET_METHOD_SM_CHAIN
     double sm_threshold;      // chain: smallest accepted |ratio| of one substitution
     int32_t sm_chunk;         // chain: determinants per independently started chain piece
+    uint32_t ev_mask;         // kernels whose events are recorded (timing)
     double *sign_out, *logabs_out, *gl_out;
     int32_t *wstatus;
 };

@@ -1714,7 +1714,7 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     const int n = a.nmax, M = a.M;
     const dim3 g2(2 * W), blk(kBlock);
     auto mark = [&](int k, bool end) {
-        if (ev) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], st);
+        if (ev && ((a.ev_mask >> k) & 1u)) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], st);
     };
     mark(0, false);
     const size_t prim_bytes = (size_t)(a.prim_dn != a.prim ? 2 : 1) * M * a.P * kPrimLdsBytes;
@@ -1765,7 +1765,7 @@ hipError_t launch_chain(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     const int W = (int)a.W;
     const dim3 g2(2 * W), blk(kBlock);
     auto mark = [&](int k, bool end) {
-        if (ev) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], st);
+        if (ev && ((a.ev_mask >> k) & 1u)) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], st);
     };
     const bool mixed = a.precision == MDET_MIXED;
     mark(7, false);
