@@ -43,8 +43,8 @@ __host__ __device__ __forceinline__ int sm_planes(int nmax, int M) {
     return 5 * (size_t)nmax * M * sizeof(double) <= 96 * 1024 ? 5 : 1;
 }
 // LDS doubles of one chain wave: inverse tile, phi_p, update factors,
-// column orbitals (16 ints), Gauss-Jordan scratch
-constexpr int kSmWaveDoubles = kMaxN * kSmLd + kMaxN + kMaxN + kMaxN / 2 + 2 * kMaxN + 2;
+// Gauss-Jordan scratch (the column orbitals stay in a register per lane)
+constexpr int kSmWaveDoubles = kMaxN * kSmLd + kMaxN + kMaxN + 2 * kMaxN + 2;
 __host__ __device__ __forceinline__ size_t sm_block_doubles(int nmax, int M) {
     return (size_t)sm_planes(nmax, M) * nmax * M + (M + 1) / 2 + (size_t)kSmWaves * kSmWaveDoubles;
 }
@@ -63,8 +63,7 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
     double *Xs = (double *)Ex + (M + 1) / 2 + (size_t)wv * kSmWaveDoubles;  // X[c][e] at c*kSmLd+e
     double *pv = Xs + kMaxN * kSmLd;                     // [16] phi_p at the electrons
     double *fv = pv + kMaxN;                             // [16] update factors
-    int *cv = (int *)(fv + kMaxN);                       // [16] column orbitals (0 beyond n)
-    double *sc = (double *)(cv + kMaxN);                 // Gauss-Jordan scratch
+    double *sc = fv + kMaxN;                             // Gauss-Jordan scratch
     const double *Pg = a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M;  // [e][5][M] unscaled
     for (int m = tid; m < M; m += 64 * kSmWaves) Ex[m] = a.wk.E[ws * M + m];
     __syncthreads();
@@ -95,7 +94,6 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
         auto restart = [&](int pos) {
             const int occ_l = lane < n ? (int)S.sm_occ[(size_t)pos * n + lane] : 0;
             for (int i = lane; i < kMaxN * kSmLd; i += 64) Xs[i] = 0.0;
-            if (lane < kMaxN) cv[lane] = occ_l;
             double rr[kMaxN];
 #pragma unroll
             for (int c = 0; c < kMaxN; ++c) rr[c] = 0.0;
@@ -141,7 +139,6 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
                 const int c = gg + 4 * j;
                 Xs[c * kSmLd + ge] -= fv[c] * xk;
             }
-            if (lane == k) cv[k] = p;
             // the sorting permutation changes parity once per other column between h and p
             const int lo = min(h, p), hi = max(h, p);
             const uint64_t between = __ballot(lane < n && lane != k && colv > lo && colv < hi);
@@ -206,15 +203,18 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
                         const double *G = Pst + ((size_t)dq * n + de) * M;
 #pragma unroll
                         for (int c = 0; c < kMaxN; c += 2) {
-                            t0 += Xs[c * kSmLd + de] * G[cv[c]];
-                            t1 += Xs[(c + 1) * kSmLd + de] * G[cv[c + 1]];
+                            t0 += Xs[c * kSmLd + de] * G[__builtin_amdgcn_readlane(colv, c)];
+                            t1 += Xs[(c + 1) * kSmLd + de] *
+                                  G[__builtin_amdgcn_readlane(colv, c + 1)];
                         }
                     } else {
                         const double *G = Pg + ((size_t)de * 5 + dq) * M;
 #pragma unroll
                         for (int c = 0; c < kMaxN; c += 2) {
-                            t0 += Xs[c * kSmLd + de] * ldexp(G[cv[c]], -Ex[cv[c]]);
-                            t1 += Xs[(c + 1) * kSmLd + de] * ldexp(G[cv[c + 1]], -Ex[cv[c + 1]]);
+                            const int m0 = __builtin_amdgcn_readlane(colv, c);
+                            const int m1 = __builtin_amdgcn_readlane(colv, c + 1);
+                            t0 += Xs[c * kSmLd + de] * ldexp(G[m0], -Ex[m0]);
+                            t1 += Xs[(c + 1) * kSmLd + de] * ldexp(G[m1], -Ex[m1]);
                         }
                     }
                     gout[(size_t)d * C4 + lane] = keep ? (F)(t0 + t1) : (F)0;
