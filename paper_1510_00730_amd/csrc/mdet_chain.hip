@@ -42,9 +42,9 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
 __host__ __device__ __forceinline__ int sm_planes(int nmax, int M) {
     return 5 * (size_t)nmax * M * sizeof(double) <= 96 * 1024 ? 5 : 1;
 }
-// LDS doubles of one chain wave: inverse tile, phi_p, update factors,
-// Gauss-Jordan scratch (the column orbitals stay in a register per lane)
-constexpr int kSmWaveDoubles = kMaxN * kSmLd + kMaxN + kMaxN + 2 * kMaxN + 2;
+// LDS doubles of one chain wave: inverse tile, update factors, Gauss-Jordan
+// scratch (the column orbitals stay in a register per lane)
+constexpr int kSmWaveDoubles = kMaxN * kSmLd + kMaxN + 2 * kMaxN + 2;
 __host__ __device__ __forceinline__ size_t sm_block_doubles(int nmax, int M) {
     return (size_t)sm_planes(nmax, M) * nmax * M + (M + 1) / 2 + (size_t)kSmWaves * kSmWaveDoubles;
 }
@@ -61,8 +61,7 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
     double *Pst = lds;                                   // [planes][n][M] scaled orbitals
     int *Ex = (int *)(Pst + (size_t)planes * nmax * M);  // [M] column exponents
     double *Xs = (double *)Ex + (M + 1) / 2 + (size_t)wv * kSmWaveDoubles;  // X[c][e] at c*kSmLd+e
-    double *pv = Xs + kMaxN * kSmLd;                     // [16] phi_p at the electrons
-    double *fv = pv + kMaxN;                             // [16] update factors
+    double *fv = Xs + kMaxN * kSmLd;                     // [16] update factors
     double *sc = fv + kMaxN;                             // Gauss-Jordan scratch
     const double *Pg = a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M;  // [e][5][M] unscaled
     for (int m = tid; m < M; m += 64 * kSmWaves) Ex[m] = a.wk.E[ws * M + m];
@@ -117,14 +116,14 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
             const uint64_t hb = __ballot(lane < n && colv == h);
             if (hb == 0) return false;  // not reached for a consistent list
             const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(hb));
-            if (lane < kMaxN) pv[lane] = lane < n ? Pst[lane * M + p] : 0.0;
-            wave_lds_sync();
+            // phi_p at the electrons, read as broadcasts from the staged orbitals
+            // (electron index clamped: the tile's columns beyond n are zero)
             double w0 = 0.0, w1 = 0.0;  // lane c < 16: (X phi_p)[c]
             if (lane < kMaxN) {
 #pragma unroll
                 for (int e = 0; e < kMaxN; e += 2) {
-                    w0 += Xs[lane * kSmLd + e] * pv[e];
-                    w1 += Xs[lane * kSmLd + e + 1] * pv[e + 1];
+                    w0 += Xs[lane * kSmLd + e] * Pst[min(e, n - 1) * M + p];
+                    w1 += Xs[lane * kSmLd + e + 1] * Pst[min(e + 1, n - 1) * M + p];
                 }
             }
             const double wc = w0 + w1;
