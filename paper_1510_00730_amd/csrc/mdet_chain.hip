@@ -49,6 +49,92 @@ __host__ __device__ __forceinline__ size_t sm_block_doubles(int nmax, int M) {
     return (size_t)sm_planes(nmax, M) * nmax * M + (M + 1) / 2 + (size_t)kSmWaves * kSmWaveDoubles;
 }
 
+// In-place Gauss-Jordan inversion with partial pivoting of the n x n matrix
+// held in the zero-padded 16 x 16 LDS tile T (row e, column c at e * kSmLd + c)
+// by the whole wave, four tile entries per lane, rows never exchanged: column
+// j's pivot is the unused row with the largest |entry| (lowest row on ties).
+// On return T holds the inverse, T[c][e] = (A^-1)[c][e], and det A = mant 2^ex
+// (sign in mant).  pr_of / j_of: the wave's 16-int LDS scratch each (pivot row
+// of column j, column pivoted by row e).  Returns false on a zero, infinite or
+// NaN pivot.  The padding stays zero throughout.
+__device__ bool tile_gauss_jordan(int n, int lane, double *T, int *pr_of, int *j_of,
+                                  double &mant_out, int &ex_out) {
+    uint32_t used = 0;
+    double mant = 1.0;
+    int ex = 0;
+    for (int j = 0; j < n; ++j) {
+        double v = -1.0;
+        if (lane < n && !((used >> lane) & 1u)) {
+            v = fabs(T[lane * kSmLd + j]);
+            if (v != v) v = INFINITY;  // NaN: pick it, then fail below
+        }
+        int id = lane;
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {  // arg max over lanes 0..15
+            const double ov = __shfl_xor(v, off, 64);
+            const int oid = __shfl_xor(id, off, 64);
+            if (ov > v || (ov == v && oid < id)) {
+                v = ov;
+                id = oid;
+            }
+        }
+        const double best = readlane_d(v, 0);
+        const int pr = __builtin_amdgcn_readlane(id, 0);
+        if (!(best > 0.0) || !(best < INFINITY)) return false;
+        used |= 1u << pr;
+        if (lane == 0) {
+            pr_of[j] = pr;
+            j_of[pr] = j;
+        }
+        const double piv = T[pr * kSmLd + j];
+        mant *= piv;
+        int kk;
+        mant = frexp(mant, &kk);
+        ex += kk;
+        const double rp = 1.0 / piv;
+        double nv[4];
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+            const int t = lane + 64 * t4, i = t >> 4, c = t & 15;
+            const double a_ic = T[i * kSmLd + c], a_pc = T[pr * kSmLd + c], a_ij = T[i * kSmLd + j];
+            if (i == pr) nv[t4] = (c == j) ? rp : a_pc * rp;
+            else nv[t4] = (c == j) ? -a_ij * rp : a_ic - a_ij * (a_pc * rp);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int t4 = 0; t4 < 4; ++t4) {
+            const int t = lane + 64 * t4;
+            T[(t >> 4) * kSmLd + (t & 15)] = nv[t4];
+        }
+        wave_lds_sync();
+    }
+    // the sweep leaves A^-1[c][e] at row pr_of[c], column j_of[e]: permute
+    double tv[4];
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4) {
+        const int t = lane + 64 * t4;
+        tv[t4] = T[(t >> 4) * kSmLd + (t & 15)];
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int t4 = 0; t4 < 4; ++t4) {
+        const int t = lane + 64 * t4, i = t >> 4, c = t & 15;
+        if (i < n && c < n) T[j_of[i] * kSmLd + pr_of[c]] = tv[t4];
+    }
+    // det A = det(permutation j -> pr_of[j]) prod pivots
+    int inv = 0;
+    if (lane < n) {
+        const int pa = pr_of[lane];
+        for (int b = lane + 1; b < n; ++b) inv += pa > pr_of[b] ? 1 : 0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) inv += __shfl_xor(inv, off, 64);
+    wave_lds_sync();
+    mant_out = (inv & 1) ? -mant : mant;
+    ex_out = ex;
+    return true;
+}
+
 template <typename F>
 __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x, lane = tid & 63;
@@ -92,14 +178,13 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
         // factorise the determinant at chain position pos from scratch
         auto restart = [&](int pos) {
             const int occ_l = lane < n ? (int)S.sm_occ[(size_t)pos * n + lane] : 0;
-            for (int i = lane; i < kMaxN * kSmLd; i += 64) Xs[i] = 0.0;
-            double rr[kMaxN];
+            // the scaled Slater matrix into the tile, zero beyond n
 #pragma unroll
-            for (int c = 0; c < kMaxN; ++c) rr[c] = 0.0;
-            if (lane < n) {
-#pragma unroll
-                for (int c = 0; c < kMaxN; ++c)
-                    if (c < n) rr[c] = Pst[lane * M + __shfl(occ_l, c, 64)];
+            for (int t4 = 0; t4 < 4; ++t4) {
+                const int t = lane + 64 * t4, e = t >> 4, c = t & 15;
+                const int m = __shfl(occ_l, c, 64);
+                const int ec = max(min(e, n - 1), 0);  // in range whatever the tile row
+                Xs[e * kSmLd + c] = (e < n && c < n) ? Pst[ec * M + m] : 0.0;
             }
             int es = lane < n ? Ex[occ_l] : 0;
 #pragma unroll
@@ -107,7 +192,7 @@ __global__ void __launch_bounds__(64 * kSmWaves) k_sm_chain(KernelArgs a, F *smg
             colv = occ_l;
             esum = es;
             wave_lds_sync();
-            have = lane_gj_core(n, lane, rr, Xs, kSmLd, sc, mant, ex);
+            have = tile_gauss_jordan(n, lane, Xs, (int *)sc, (int *)sc + kMaxN, mant, ex);
             wave_lds_sync();
         };
 
