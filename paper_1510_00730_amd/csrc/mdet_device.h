@@ -20,10 +20,19 @@ __device__ __forceinline__ size_t rv_index(const KernelArgs &a, int sp, int d, i
 }
 
 // psi of walker w: the row-split partial sums of the sparse combination
-// (accumulated in FP64 in both precisions), added in a fixed order
+// (accumulated in FP64 in both precisions), added in a fixed order.  All
+// kPsiParts slots are loaded at once (indices clamped to the used ones) so
+// that the loads are in flight together, not one round trip per part.
 __device__ __forceinline__ double psi_value(const KernelArgs &a, int w) {
+    const double *p = a.wk.psi64 + (size_t)w * kPsiParts;
+    const int np = a.psi_nparts, last = np > 0 ? np - 1 : 0;
+    double v[kPsiParts];
+#pragma unroll
+    for (int k = 0; k < kPsiParts; ++k) v[k] = p[k < np ? k : last];
     double s = 0.0;
-    for (int k = 0; k < a.psi_nparts; ++k) s += a.wk.psi64[(size_t)w * kPsiParts + k];
+#pragma unroll
+    for (int k = 0; k < kPsiParts; ++k)
+        if (k < np) s += v[k];
     return s;
 }
 

@@ -451,15 +451,30 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     int *slot = emax + 2 * M;         // [2][M] reference slot of orbital m, or -1
     double *pw = (double *)(slot + 2 * M);  // [N][3][kPowLd] coordinate powers
     double *r2s = pw + N * 3 * kPowLd;      // [N] |r|^2
+    int *occl = (int *)(r2s + N);           // [2][kMaxN] reference occupations
+    // the set-up's loads issued before any is used: the walker's coordinates
+    // (one per thread, N * 3 <= kBlock) and the reference occupations
+    const double *Rw = a.R + (size_t)w * N * 3;
+    const int nocc = a.sp[0].n + a.sp[1].n;
+    const double xv = tid < N * 3 ? Rw[tid] : 0.0;
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (tid < N) {
+        rx = Rw[3 * tid];
+        ry = Rw[3 * tid + 1];
+        rz = Rw[3 * tid + 2];
+    }
+    const int osp = tid >= nup ? 1 : 0, oc = tid - (osp ? nup : 0);
+    const int ov = tid < nocc ? a.sp[osp].occ0[oc] : 0;
     // the primitives (one set, or one per spin), staged as [set][p][m] arrays
     // when they fit (else read from HBM): consecutive orbitals in consecutive
     // LDS words
     const int MP = M * a.P;
     const int nsets = a.prim_dn != a.prim ? 2 : 1;
     const bool stage_prim = (size_t)nsets * MP * kPrimLdsBytes <= kPrimLdsMax;
-    double *p_al = r2s + N, *p_cf = p_al + nsets * MP;
+    double *p_al = (double *)(occl + 2 * kMaxN), *p_cf = p_al + nsets * MP;
     int *p_abc = (int *)(p_cf + nsets * MP);
     if (stage_prim)
+#pragma unroll 4
         for (int i = tid; i < nsets * MP; i += kBlock) {
             const int set = i >= MP, j = i - set * MP;
             const int m = j / a.P, p = j - m * a.P;
@@ -476,26 +491,21 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         slot[i] = -1;
     }
     __syncthreads();
-    const double *Rw = a.R + (size_t)w * N * 3;
-    for (int i = tid; i < a.sp[0].n + a.sp[1].n; i += kBlock) {
-        const int sp = i >= nup, c = i - (sp ? nup : 0);
-        slot[sp * M + a.sp[sp].occ0[c]] = c;
+    if (tid < nocc) {
+        slot[osp * M + ov] = oc;
+        occl[osp * kMaxN + oc] = ov;
     }
-    for (int i = tid; i < N * 3; i += kBlock) {
-        const double x = Rw[i];
-        double *t = pw + i * kPowLd;
+    if (tid < N * 3) {
+        double *t = pw + tid * kPowLd;
         t[0] = 0.0;
         t[1] = 0.0;
         double p = 1.0;
         for (int k = 0; k <= 6; ++k) {
             t[2 + k] = p;
-            p *= x;
+            p *= xv;
         }
     }
-    for (int e = tid; e < N; e += kBlock) {
-        const double *r = Rw + 3 * e;
-        r2s[e] = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-    }
+    if (tid < N) r2s[tid] = rx * rx + ry * ry + rz * rz;
     __syncthreads();
     double *phig = a.wk.phi + (size_t)w * N * 5 * M;
     // orbitals and derivatives, written once (unscaled)
@@ -536,7 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     for (int i = tid; i < 10 * nn; i += kBlock) {
         const int sp = i / (5 * nn), r = i % nn;
         const int n = a.sp[sp].n;
-        if (r < n * n) Q[i] *= pow2(-emax[sp * M + a.sp[sp].occ0[r % n]]);
+        if (r < n * n) Q[i] *= pow2(-emax[sp * M + occl[sp * kMaxN + r % n]]);
     }
     __syncthreads();
     // one wave per spin from here on
@@ -561,7 +571,7 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     }
     if (lane == 0) {
         int sx = 0;
-        for (int c = 0; c < n; ++c) sx += emax[sp * M + S.occ0[c]];
+        for (int c = 0; c < n; ++c) sx += emax[sp * M + occl[sp * kMaxN + c]];
         a.wk.logdet0[ws] = la + (double)sx * 0.69314718055994530942;
         a.wk.sign0[ws] = sg;
     }
@@ -637,22 +647,55 @@ namespace {
 
 // T = X Phi' of one (walker, spin) into LDS: T[c][m] = sum_e X[c][e] phi[e][m] 2^-E[m]
 // (X in LDS, row-major n x n; phis = values of the spin's first electron, row
-// stride 5 M).  One column m per thread, e ascending.
-__device__ __forceinline__ void build_table(const double *phis, int n, int M, const int *Ex,
-                                            const double *X, double *T, int tid, int nthr) {
-    for (int m = tid; m < M; m += nthr) {
-        const double s = pow2(-Ex[m]);
-        double col[kMaxN];
+// stride 5 M).  One column m per thread, e ascending.  The values of column
+// m = tid come in `col0`, loaded by pair_setup before the set-up barrier.
+__device__ __forceinline__ void table_column_load(const double *phis, int n, int M, int m,
+                                                  double col[kMaxN]) {
 #pragma unroll
-        for (int e = 0; e < kMaxN; ++e) col[e] = (e < n) ? phis[(size_t)e * 5 * M + m] * s : 0.0;
-        for (int c = 0; c < n; ++c) {
-            double t = 0.0;
+    for (int e = 0; e < kMaxN; ++e) col[e] = (e < n && m < M) ? phis[(size_t)e * 5 * M + m] : 0.0;
+}
+
+__device__ __forceinline__ void table_column(int n, int M, int m, const int *Ex, const double *X,
+                                             double col[kMaxN], double *T) {
+    const double s = pow2(-Ex[m]);
 #pragma unroll
-            for (int e = 0; e < kMaxN; ++e)
-                if (e < n) t += X[c * n + e] * col[e];
-            T[c * M + m] = t;
-        }
+    for (int e = 0; e < kMaxN; ++e) col[e] *= s;
+    for (int c = 0; c < n; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int e = 0; e < kMaxN; ++e)
+            if (e < n) t += X[c * n + e] * col[e];
+        T[c * M + m] = t;
     }
+}
+
+__device__ __forceinline__ void build_table(const double *phis, int n, int M, const int *Ex,
+                                            const double *X, double *T, int tid, int nthr,
+                                            double col0[kMaxN]) {
+    if (tid < M) table_column(n, M, tid, Ex, X, col0, T);
+    for (int m = tid + nthr; m < M; m += nthr) {
+        double col[kMaxN];
+        table_column_load(phis, n, M, m, col);
+        table_column(n, M, m, Ex, X, col, T);
+    }
+}
+
+// Set-up of the kernels that rebuild T for one (walker, spin): X, the column
+// exponents and the reference occupation into LDS, and the orbital values of
+// the thread's first table column into col0, every load issued before the
+// first is waited for (one round trip to memory, not one per array).
+static_assert(kMaxN * kMaxN <= kBlock, "one X entry per thread");
+__device__ __forceinline__ void pair_setup(const double *Xg, const int *Eg, const int *occg,
+                                           const double *phis, int n, int M, int tid, double *X,
+                                           int *Ex, int *occ0, double col0[kMaxN]) {
+    const double xv = tid < n * n ? Xg[tid] : 0.0;
+    const int ev = tid < M ? Eg[tid] : 0;
+    const int ov = tid < n ? occg[tid] : 0;
+    table_column_load(phis, n, M, tid, col0);
+    if (tid < n * n) X[tid] = xv;
+    if (tid < M) Ex[tid] = ev;
+    if (tid < n) occ0[tid] = ov;
+    for (int m = tid + kBlock; m < M; m += kBlock) Ex[m] = Eg[m];
 }
 
 }  // namespace
@@ -676,12 +719,12 @@ __global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
     int *Ex = (int *)(X + n * n);    // [M]
     int *occ0 = Ex + M;              // [n]
     __shared__ int red[kBlock];
-    const double *Xg = a.wk.X + ws * a.nmax * a.nmax;
-    for (int i = tid; i < n * n; i += kBlock) X[i] = Xg[i];
-    for (int m = tid; m < M; m += kBlock) Ex[m] = a.wk.E[ws * M + m];
-    for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
+    const double *phis = a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M;
+    double col0[kMaxN];
+    pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
+               occ0, col0);
     __syncthreads();
-    build_table(a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M, n, M, Ex, X, T, tid, kBlock);
+    build_table(phis, n, M, Ex, X, T, tid, kBlock, col0);
     __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const bool mixed = a.precision == MDET_MIXED;
@@ -961,13 +1004,13 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
     double *scr = Zc + n * n;         // [kDerivScratch]
     int *Ex = (int *)(un + deriv_union_doubles(n, M));  // [M]
     int *occ0 = Ex + M;               // [n]
+    const double *phis = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
+    double col0[kMaxN];
+    pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
+               occ0, col0);
     for (int i = tid; i < nt; i += kBlock) Gam[i] = 0.0;
-    const double *Xg = a.wk.X + ws * a.nmax * a.nmax;
-    for (int i = tid; i < n * n; i += kBlock) X[i] = Xg[i];
-    for (int m = tid; m < M; m += kBlock) Ex[m] = a.wk.E[ws * M + m];
-    for (int c = tid; c < n; c += kBlock) occ0[c] = S.occ0[c];
     __syncthreads();
-    build_table(a.wk.phi + ((size_t)w * N + S.e0) * 5 * M, n, M, Ex, X, T, tid, kBlock);
+    build_table(phis, n, M, Ex, X, T, tid, kBlock, col0);
     __syncthreads();
     const int K = a.wk.K[ws];
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
@@ -1105,11 +1148,19 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
     if (tid < 4 * n) {
         const int e = tid >> 2, q = tid & 3;
         const double *Gq = phig + (size_t)e * 5 * M + (size_t)(1 + q) * M;
+        const size_t o = ((size_t)w * N + S.e0 + e) * 4 + q;
+        // the phase's loads issued together (occupied columns clamped to n)
+        double go[kMaxN];
+#pragma unroll
+        for (int c = 0; c < kMaxN; ++c) go[c] = Gq[occ0[c < n ? c : n - 1]];
+        const double g0 = a.wk.g0[o];
+        const double psi = psi_value(a, w);
         double s1 = 0.0, s2 = 0.0;
         for (int g = 0; g < nf; ++g) s1 += scr[tid * nf + g];
-        for (int c = 0; c < n; ++c) s2 += (Gq[occ0[c]] * pow2(-Ex[occ0[c]])) * Zc[c * n + e];
-        const size_t o = ((size_t)w * N + S.e0 + e) * 4 + q;
-        a.gl_out[o] = a.wk.g0[o] + (s1 - s2) / psi_value(a, w);
+#pragma unroll
+        for (int c = 0; c < kMaxN; ++c)
+            if (c < n) s2 += (go[c] * pow2(-Ex[occ0[c]])) * Zc[c * n + e];
+        a.gl_out[o] = g0 + (s1 - s2) / psi;
     }
 }
 
@@ -1515,9 +1566,15 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a) {
     if (node) {
         a.gl_out[i] = 0.0;
     } else if (!chain && a.wk.flag[2 * w + sp] != 0) {
+        const int np = a.direct_split, last = np > 0 ? np - 1 : 0;
+        double v[kDirectSplitMax];
+#pragma unroll
+        for (int p = 0; p < kDirectSplitMax; ++p)
+            v[p] = a.wk.dpart[((size_t)w * kDirectSplitMax + (p < np ? p : last)) * per + t];
         double s = 0.0;
-        for (int p = 0; p < a.direct_split; ++p)
-            s += a.wk.dpart[((size_t)w * kDirectSplitMax + p) * per + t];
+#pragma unroll
+        for (int p = 0; p < kDirectSplitMax; ++p)
+            if (p < np) s += v[p];
         a.gl_out[i] = s / psi;
     }
     if (t != 0) return;
@@ -1720,7 +1777,8 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     const size_t prim_bytes = (size_t)(a.prim_dn != a.prim ? 2 : 1) * M * a.P * kPrimLdsBytes;
     const size_t lds_ref = sizeof(double) * (14 * (size_t)n * n + 2 * (2 * kMaxN + 2) +
                                              (size_t)a.N * (3 * kPowLd + 1)) +
-                           sizeof(int) * 4 * (size_t)M + (prim_bytes <= kPrimLdsMax ? prim_bytes : 0);
+                           sizeof(int) * (4 * (size_t)M + 2 * kMaxN) +
+                           (prim_bytes <= kPrimLdsMax ? prim_bytes : 0);
     k_reference<<<dim3(W), blk, lds_ref, st>>>(a);
     mark(0, true);
     if (a.method == MDET_METHOD_SM_CHAIN) return launch_chain(a, st, ev);
