@@ -702,9 +702,11 @@ __device__ __forceinline__ void pair_setup(const double *Xg, const int *Eg, cons
 
 // ---------------------------------------------------------------------------
 // K4: ratios R_d / 2^K of every distinct determinant (table method).
-// One block per (walker, spin); one thread per determinant.
+// One block per (walker, spin); one thread per determinant.  Eight waves per
+// SIMD (at most 64 VGPRs) let all pairs of a 1024-walker batch be resident
+// at once.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(kBlock) k_ratios(KernelArgs a) {
+__global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
     const size_t ws = (size_t)w * 2 + sp;
     if (a.wk.flag[ws] != 0) {  // ill-conditioned: queue the pair for the direct-LU fallback
