@@ -169,6 +169,16 @@ __device__ __forceinline__ int delta_exponent(const DetDesc &D, const int *Ex, c
     return dx;
 }
 
+// the same for a known degree S (static descriptor indices, all LDS reads
+// issued together)
+template <int S>
+__device__ __forceinline__ int delta_exponent_t(const DetDesc &D, const int *Ex, const int *occ0) {
+    int dx = 0;
+#pragma unroll
+    for (int a = 0; a < S; ++a) dx += Ex[D.p[a]] - Ex[occ0[D.h[a]]];
+    return dx;
+}
+
 // Gauss-Jordan inversion with partial pivoting of an S x S matrix (row-major),
 // fully unrolled so the matrix lives in registers.  Returns false on an exactly
 // zero pivot.  det receives the determinant (product of pivots and row-swap signs).
@@ -744,8 +754,13 @@ __global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
         if (d < S.U) {
             const DetDesc D = S.desc[d];
             if (D.s <= dmax) {
-                r = ratio_any(D, T, M);
-                dx = delta_exponent(D, Ex, occ0);
+                switch (D.s) {
+                case 0: r = (double)D.eps; break;
+                case 1: r = exc_ratio<1>(D, T, M); dx = delta_exponent_t<1>(D, Ex, occ0); break;
+                case 2: r = exc_ratio<2>(D, T, M); dx = delta_exponent_t<2>(D, Ex, occ0); break;
+                case 3: r = exc_ratio<3>(D, T, M); dx = delta_exponent_t<3>(D, Ex, occ0); break;
+                default: r = exc_ratio<4>(D, T, M); dx = delta_exponent_t<4>(D, Ex, occ0); break;
+                }
                 if (r != 0.0) kmax = max(kmax, expo(r) + dx);
             }
         }
