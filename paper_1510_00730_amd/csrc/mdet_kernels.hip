@@ -115,7 +115,7 @@ __device__ int block_max_int(int v, int *red) {
     return r;
 }
 
-// small determinants and cofactors (s <= 4), row-major s x s
+// small determinants, row-major
 __device__ __forceinline__ double det2(double a, double b, double c, double d) {
     return a * d - b * c;
 }
@@ -124,43 +124,6 @@ __device__ double det3(const double *m, int ld) {
     return m[0] * det2(m[ld + 1], m[ld + 2], m[2 * ld + 1], m[2 * ld + 2]) -
            m[1] * det2(m[ld + 0], m[ld + 2], m[2 * ld + 0], m[2 * ld + 2]) +
            m[2] * det2(m[ld + 0], m[ld + 1], m[2 * ld + 0], m[2 * ld + 1]);
-}
-
-__device__ double small_det(const double *m, int s) {
-    switch (s) {
-    case 0: return 1.0;
-    case 1: return m[0];
-    case 2: return det2(m[0], m[1], m[2], m[3]);
-    case 3: return det3(m, 3);
-    default: {
-        // Laplace expansion along the first two rows (products of 2x2 minors)
-        const double *r0 = m, *r1 = m + 4, *r2 = m + 8, *r3 = m + 12;
-        double acc = 0.0;
-        const int pr[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
-        const double sg[6] = {1, -1, 1, 1, -1, 1};
-        for (int t = 0; t < 6; ++t) {
-            const int i = pr[t][0], j = pr[t][1];
-            const int k = pr[5 - t][0], l = pr[5 - t][1];
-            acc += sg[t] * det2(r0[i], r0[j], r1[i], r1[j]) * det2(r2[k], r2[l], r3[k], r3[l]);
-        }
-        return acc;
-    }
-    }
-}
-
-// cofactor C_{ab} = (-1)^{a+b} det(m without row a, column b)
-__device__ double cofactor(const double *m, int s, int a, int b) {
-    double sub[9];
-    int t = 0;
-    for (int i = 0; i < s; ++i) {
-        if (i == a) continue;
-        for (int j = 0; j < s; ++j) {
-            if (j == b) continue;
-            sub[t++] = m[i * s + j];
-        }
-    }
-    const double d = small_det(sub, s - 1);
-    return ((a + b) & 1) ? -d : d;
 }
 
 __device__ __forceinline__ int delta_exponent(const DetDesc &D, const int *Ex, const int *occ0) {
@@ -177,71 +140,6 @@ __device__ __forceinline__ int delta_exponent_t(const DetDesc &D, const int *Ex,
 #pragma unroll
     for (int a = 0; a < S; ++a) dx += Ex[D.p[a]] - Ex[occ0[D.h[a]]];
     return dx;
-}
-
-// Gauss-Jordan inversion with partial pivoting of an S x S matrix (row-major),
-// fully unrolled so the matrix lives in registers.  Returns false on an exactly
-// zero pivot.  det receives the determinant (product of pivots and row-swap signs).
-template <int S>
-__device__ __forceinline__ bool gj_inverse(const double *m, double *inv, double &det) {
-    double a[S][S], b[S][S];
-#pragma unroll
-    for (int i = 0; i < S; ++i)
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            a[i][k] = m[i * S + k];
-            b[i][k] = (i == k) ? 1.0 : 0.0;
-        }
-    det = 1.0;
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-        int p = j;
-        double best = fabs(a[j][j]);
-#pragma unroll
-        for (int i = j + 1; i < S; ++i)
-            if (fabs(a[i][j]) > best) {
-                best = fabs(a[i][j]);
-                p = i;
-            }
-        if (!(best > 0.0)) return false;
-#pragma unroll
-        for (int i = j + 1; i < S; ++i)
-            if (i == p) {
-#pragma unroll
-                for (int k = 0; k < S; ++k) {
-                    double t = a[i][k];
-                    a[i][k] = a[j][k];
-                    a[j][k] = t;
-                    t = b[i][k];
-                    b[i][k] = b[j][k];
-                    b[j][k] = t;
-                }
-                det = -det;
-            }
-        const double piv = a[j][j];
-        det *= piv;
-        const double r = 1.0 / piv;
-#pragma unroll
-        for (int k = 0; k < S; ++k) {
-            a[j][k] *= r;
-            b[j][k] *= r;
-        }
-#pragma unroll
-        for (int i = 0; i < S; ++i) {
-            if (i == j) continue;
-            const double f = a[i][j];
-#pragma unroll
-            for (int k = 0; k < S; ++k) {
-                a[i][k] -= f * a[j][k];
-                b[i][k] -= f * b[j][k];
-            }
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < S; ++i)
-#pragma unroll
-        for (int k = 0; k < S; ++k) inv[i * S + k] = b[i][k];
-    return true;
 }
 
 // a / b from the correctly rounded reciprocal rb = 1 / b and one FMA
@@ -312,6 +210,7 @@ __device__ __forceinline__ double exc_ratio(const DetDesc &D, const double *T, i
     double d;
     if constexpr (S == 1) d = m[0];
     else if constexpr (S == 2) d = det2(m[0], m[1], m[2], m[3]);
+    else if constexpr (S == 3) d = det3(m, 3);
     else d = det_lu<S>(m);
     return (double)D.eps * d;
 }
@@ -387,6 +286,27 @@ __device__ __forceinline__ bool gj_inplace(double (&a)[S][S], double &det) {
     return true;
 }
 
+// coef * C_ab of an exactly singular 4 x 4 minor (Gauss-Jordan met a zero
+// pivot): each cofactor from its 3 x 3 determinant.  Out of line: the case is
+// rare and its registers stay out of the callers' hot path.
+__device__ __noinline__ void adj4_singular(DetDesc D, const double *T, int M, double coef,
+                                           double *dst) {
+    double e[16];
+    load_exc<4>(D, T, M, e);
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) {
+            double sub[9];
+            int t = 0;
+            for (int i = 0; i < 4; ++i) {
+                if (i == r) continue;
+                for (int j = 0; j < 4; ++j)
+                    if (j != c) sub[t++] = e[i * 4 + j];
+            }
+            const double d = det3(sub, 3);
+            dst[r * 4 + c] = coef * (((r + c) & 1) ? -d : d);
+        }
+}
+
 // coef * C_ab of M_d into dst[a*S + b] (C_ab = adj[b][a]), compile-time s
 template <int S>
 __device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int M, double coef,
@@ -400,24 +320,37 @@ __device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int
         dst[1] = -coef * m[2];
         dst[2] = -coef * m[1];
         dst[3] = coef * m[0];
+    } else if constexpr (S == 3) {
+        // cofactors from 2 x 2 minors (no division, defined for any minor)
+        double m[9];
+        load_exc<3>(D, T, M, m);
+        dst[0] = coef * (m[4] * m[8] - m[5] * m[7]);
+        dst[1] = coef * (m[5] * m[6] - m[3] * m[8]);
+        dst[2] = coef * (m[3] * m[7] - m[4] * m[6]);
+        dst[3] = coef * (m[2] * m[7] - m[1] * m[8]);
+        dst[4] = coef * (m[0] * m[8] - m[2] * m[6]);
+        dst[5] = coef * (m[1] * m[6] - m[0] * m[7]);
+        dst[6] = coef * (m[1] * m[5] - m[2] * m[4]);
+        dst[7] = coef * (m[2] * m[3] - m[0] * m[5]);
+        dst[8] = coef * (m[0] * m[4] - m[1] * m[3]);
     } else {
-        double a[S][S];
+        // det M times M^-1 by pivoted Gauss-Jordan (cofactors from 2 x 2
+        // minors cost less but lose accuracy on these minors, whose entries
+        // cancel); the cofactor form serves only an exactly singular minor
+        double a[4][4];
 #pragma unroll
-        for (int i = 0; i < S; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int k = 0; k < S; ++k) a[i][k] = T[D.h[i] * M + D.p[k]];
+            for (int k = 0; k < 4; ++k) a[i][k] = T[D.h[i] * M + D.p[k]];
         double det = 0.0;
-        if (gj_inplace<S>(a, det)) {
+        if (gj_inplace<4>(a, det)) {
             const double cd = coef * det;  // adj = det * inverse; C_ab = adj[b][a]
 #pragma unroll
-            for (int i = 0; i < S; ++i)
+            for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int k = 0; k < S; ++k) dst[i * S + k] = cd * a[k][i];
-        } else {  // exactly singular: explicit cofactors
-            double m[S * S];
-            load_exc<S>(D, T, M, m);
-            for (int a2 = 0; a2 < S; ++a2)
-                for (int b2 = 0; b2 < S; ++b2) dst[a2 * S + b2] = coef * cofactor(m, S, a2, b2);
+                for (int k = 0; k < 4; ++k) dst[i * 4 + k] = cd * a[k][i];
+        } else {
+            adj4_singular(D, T, M, coef, dst);
         }
     }
 }
