@@ -39,10 +39,13 @@ __device__ __forceinline__ double pow2(int k) { return ldexp(1.0, k); }
 // P_k = x^k:  d0 = P_a,  d1 = a P_(a-1) - 2 alpha P_(a+1),
 // d2 = a (a-1) P_(a-2) - 2 alpha (2a+1) P_a + 4 alpha^2 P_(a+2)
 // (the derivatives of x^a e^(-alpha x^2), divided by e^(-alpha x^2)).  The
-// powers come from a table: pw[axis * kPowLd + 2 + k] = P_k for k = 0..6 and 0
-// for k = -2, -1, so the terms with a negative power vanish without a branch
-// (no 0 * inf at a coordinate 0); r2 = |r|^2.
-constexpr int kPowLd = 9;
+// alpha-free factors come from a per-electron table, for each axis and power
+// a = 0..4: pw[axis * kPowLd + 6 a + (0..5)] = P_a, a P_(a-1), P_(a+1),
+// a (a-1) P_(a-2), (2a+1) P_a, P_(a+2), with P_(-1) = P_(-2) = 0 so the
+// terms with a negative power vanish without a branch (no 0 * inf at a
+// coordinate 0); then d1 = A1 - 2 alpha B1 and d2 = A2 - 2 alpha B2 +
+// 4 alpha^2 C2 per primitive.  r2 = |r|^2.
+constexpr int kPowLd = 30;
 constexpr size_t kPrimLdsMax = 32 * 1024;  // LDS for the primitives in the orbital kernel
 constexpr size_t kPrimLdsBytes = 2 * sizeof(double) + sizeof(int);  // per primitive
 
@@ -75,11 +78,10 @@ __device__ __forceinline__ void orbital5_tab(const Prim *prim, const double *s_a
         double f[3][3];
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-            const double *P0 = pw + ax * kPowLd + 2 + pa[ax];
-            const double da = (double)pa[ax];
-            f[ax][0] = P0[0];
-            f[ax][1] = da * P0[-1] - t2 * P0[1];
-            f[ax][2] = da * (da - 1.0) * P0[-2] - t2 * (2.0 * da + 1.0) * P0[0] + t4 * P0[2];
+            const double *Q = pw + ax * kPowLd + 6 * pa[ax];
+            f[ax][0] = Q[0];
+            f[ax][1] = Q[1] - t2 * Q[2];
+            f[ax][2] = Q[3] - t2 * Q[4] + t4 * Q[5];
         }
         const double yz = f[1][0] * f[2][0];
         v += g * f[0][0] * yz;
@@ -392,7 +394,7 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     double *gsc = Rl + 2 * nn;        // [2][2 kMaxN + 2] Gauss-Jordan scratch per wave
     int *emax = (int *)(gsc + 2 * (2 * kMaxN + 2));  // [2][M] largest exponent of |phi| per column
     int *slot = emax + 2 * M;         // [2][M] reference slot of orbital m, or -1
-    double *pw = (double *)(slot + 2 * M);  // [N][3][kPowLd] coordinate powers
+    double *pw = (double *)(slot + 2 * M);  // [N][3][kPowLd] coordinate power factors
     double *r2s = pw + N * 3 * kPowLd;      // [N] |r|^2
     int *occl = (int *)(r2s + N);           // [2][kMaxN] reference occupations
     // the set-up's loads issued before any is used: the walker's coordinates
@@ -439,13 +441,25 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
         occl[osp * kMaxN + oc] = ov;
     }
     if (tid < N * 3) {
-        double *t = pw + tid * kPowLd;
-        t[0] = 0.0;
-        t[1] = 0.0;
+        double P[9];  // P[2 + k] = x^k, k = -2..6
+        P[0] = 0.0;
+        P[1] = 0.0;
         double p = 1.0;
+#pragma unroll
         for (int k = 0; k <= 6; ++k) {
-            t[2 + k] = p;
+            P[2 + k] = p;
             p *= xv;
+        }
+        double *t = pw + tid * kPowLd;
+#pragma unroll
+        for (int a = 0; a <= 4; ++a) {
+            const double da = (double)a;
+            t[6 * a + 0] = P[2 + a];
+            t[6 * a + 1] = da * P[1 + a];
+            t[6 * a + 2] = P[3 + a];
+            t[6 * a + 3] = da * (da - 1.0) * P[a];
+            t[6 * a + 4] = (2.0 * da + 1.0) * P[2 + a];
+            t[6 * a + 5] = P[4 + a];
         }
     }
     if (tid < N) r2s[tid] = rx * rx + ry * ry + rz * rz;
