@@ -219,3 +219,33 @@ def test_indexing_on_device_context_matches_oracle():
     ref = pp.index_expansion(wl.det_up, wl.det_dn, wl.c)
     for k in ("uniq_up", "uniq_dn", "row_i", "col_j", "src_pos"):
         assert np.array_equal(got[k], ref[k]), k
+
+
+def test_identically_zero_orbital_gives_singular_minors():
+    """A virtual orbital with all coefficients zero vanishes identically, so
+    every excitation into it has an exactly singular minor (a zero column):
+    the table method's ratio is zero and its degree-4 cofactors take the
+    out-of-line path for singular minors.  The determinant and its
+    derivatives are identically zero, as in the oracle."""
+    from oracle.preprocess import occupied
+    log("[parity] identically zero virtual orbital, degrees 2-4")
+    wl = make_custom(9, 8, 40, 3, 150, 120, (2, 3, 4), 3000, 64, seed=41)
+    ref_up = set(occupied(wl.det_up[0]))
+    ref_dn = set(occupied(wl.det_dn[0]))
+    quad = {}
+    for words in np.unique(wl.det_up, axis=0):
+        occ = set(occupied(words))
+        parts = occ - ref_up
+        if len(parts) == 4:
+            for m in parts - ref_dn:
+                quad[m] = quad.get(m, 0) + 1
+    m0 = max(quad, key=quad.get)
+    assert quad[m0] >= 3  # several degree-4 minors get a zero column
+    wl.coef[m0, :] = 0.0
+    ev = evaluator(wl)
+    ref = oracle.evaluate(wl, n_threads=16)
+    for prec, tol in ((mdet.MDET_FP64, FP64_TOL), (mdet.MDET_MIXED, MIXED_TOL)):
+        sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=prec)
+        ep, eg = scaled_errors(ref, sign, logabs, gl)
+        summary(f"zero orbital {m0} precision {prec}", ep, eg, ws)
+        assert ep.max() <= tol and eg.max() <= tol
