@@ -6,7 +6,11 @@ TEST INFRASTRUCTURE ONLY.
   definition, used to check the oracle's LU determinants and its derivative
   ratios through the row-replacement identity grad~_e D = det(S with row e
   replaced by the derivative row).
-* Eq. (1) by brute force: loop over the products, Leibniz per determinant.
+* Eq. (1) by brute force: loop over the products, Leibniz per determinant,
+  together with the sums of the absolute values of its terms (the error
+  scales S_Psi = sum_k |c_k D_up D_dn| and, per electron and component,
+  S_grad = sum_k |c_k grad~(D_up D_dn)|, over the terms of Eq. (1) and of
+  Eq. (nabla), Sec. 2.3).
 """
 from __future__ import annotations
 
@@ -54,8 +58,11 @@ def det_and_grad(S, G):
     return D, g
 
 
-def psi_brute(wl, Rw):
-    """Psi and grad~Psi (unnormalised, FP64, no scaling) by Eq. (1) with Leibniz."""
+def psi_brute(wl, Rw, with_abs=False):
+    """Psi and grad~Psi (unnormalised, FP64, no scaling) by Eq. (1) with Leibniz.
+
+    With ``with_abs`` also S_Psi and S_grad [N][4], the sums of the absolute
+    values of the terms of Psi and of each component of grad~Psi."""
     N = wl.n_up + wl.n_dn
     orb = np.array([_orbitals(wl, Rw[e], spin=int(e >= wl.n_up)) for e in range(N)])  # [N][5][M]
     cache = {}
@@ -71,12 +78,20 @@ def psi_brute(wl, Rw):
 
     psi = 0.0
     grad = np.zeros((N, 4))
+    s_psi = 0.0
+    s_grad = np.zeros((N, 4))
     for k in range(wl.n_det):
         Du, gu = spin_det(wl.det_up[k], 0, wl.n_up)
         Dd, gd = spin_det(wl.det_dn[k], wl.n_up, wl.n_dn)
         psi += wl.c[k] * Du * Dd
         grad[:wl.n_up] += wl.c[k] * gu * Dd
         grad[wl.n_up:] += wl.c[k] * Du * gd
+        # product rule: an up electron's derivative only touches D_up
+        s_psi += abs(wl.c[k] * Du * Dd)
+        s_grad[:wl.n_up] += np.abs(wl.c[k] * gu * Dd)
+        s_grad[wl.n_up:] += np.abs(wl.c[k] * Du * gd)
+    if with_abs:
+        return psi, grad, s_psi, s_grad
     return psi, grad
 
 

@@ -20,6 +20,13 @@ MUTATIONS = {
     "pivot_sign_dropped": ("if (d < 0) sg = -sg;", ";"),
     "column_scale_dropped": ("*logabs = la + colexp_sum * log(2.0);", "*logabs = la;"),
     "wrong_spin_ratio": ("double x = term * rd[e * 4 + q];", "double x = term * rt_u[e * 4 + q];"),
+    # the error scales (denominators of every parity gate)
+    "error_scale_psi_inflated": ("aabs[0] += fabs(term);", "aabs[0] += 1000.0 * fabs(term);"),
+    "error_scale_psi_coef_only": ("aabs[0] += fabs(term);",
+                                  "aabs[0] += fabs(c[k]);"),
+    "error_scale_grad_inflated": ("aabs[1 + e * 4 + q] += fabs(x);",
+                                  "aabs[1 + e * 4 + q] += 1000.0 * fabs(x);"),
+    "error_scale_grad_dn_dropped": ("aabs[1 + (n_up + e) * 4 + q] += fabs(x);", ";"),
 }
 
 

@@ -145,6 +145,22 @@ def test_tiny_config_vs_leibniz_brute_force():
         assert ep < 1e-12 and eg < 1e-12, (w, ep, eg)
 
 
+def test_error_scales_vs_brute_force():
+    """rs_psi = S_Psi / |Psi| and rs_gl = S_grad / |Psi|, with S the sums of
+    the absolute values of the terms of Eq. (1) and of Eq. (nabla) (Sec. 2.3),
+    recomputed product by product with Leibniz determinants.  These scales are
+    the denominators of every parity gate, so they are pinned here."""
+    wl = make_config(1)
+    res = oracle.evaluate(wl, n_threads=2)
+    for w in range(wl.n_walk):
+        psi, _, s_psi, s_grad = brute.psi_brute(wl, wl.R[w], with_abs=True)
+        assert abs(res.rs_psi[w] - s_psi / abs(psi)) <= 1e-12 * res.rs_psi[w], w
+        np.testing.assert_allclose(res.rs_gl[w], s_grad / abs(psi), rtol=1e-12, atol=0)
+        # a sum of absolute values bounds the absolute value of the sum
+        assert res.rs_psi[w] >= 1.0 - 1e-14
+        assert np.all(res.rs_gl[w] * abs(psi) >= np.abs(res.gl[w] * psi) * (1 - 1e-12))
+
+
 def _cauchy_binet_case(n_mo, n_up, n_dn, n_walk, seed):
     base = make_custom(n_up, n_dn, n_mo, 3, 2, 2, (1,), 1, n_walk, sigma=1.0, seed=seed,
                        alpha_range=(0.2, 2.0))
@@ -187,6 +203,39 @@ def test_cauchy_binet_full_ci(shape):
         assert res.sign[w] == sgn
         assert abs(res.logabs[w] - logabs) < 1e-11 * (1 + res.rs_psi[w])
         np.testing.assert_allclose(res.gl[w], gl, rtol=0, atol=1e-10 * (1 + np.abs(gl).max()))
+
+
+def test_error_scales_cauchy_binet_closed_form():
+    """For c_IJ = det B_up[I] det B_dn[J] the absolute-term sums factorise:
+    S_Psi = S_up S_dn with S_sigma = sum_I |det B_sigma[I]| |det Phi_sigma[:, I]|,
+    and for an up electron S_grad[e,q] = (sum_I |det B_up[I]| |grad~_eq det
+    Phi_up[:, I]|) S_dn, the derivative determinant taken by row replacement
+    (numpy LU, independent of the oracle).  Checks rs_psi and rs_gl at the
+    scale of hundreds of products."""
+    n_mo, n_up, n_dn, W = 8, 4, 3, 3
+    wl, Bu, Bd = _cauchy_binet_case(n_mo, n_up, n_dn, W, seed=n_mo)
+    res = oracle.evaluate(wl, n_threads=4)
+    for w in range(W):
+        orb = np.array([oracle.orbitals(wl, wl.R[w, e]) for e in range(wl.n_elec)])
+        S_spin, G_spin, psi = [], [], 1.0
+        for e0, n, B in ((0, n_up, Bu), (n_up, n_dn, Bd)):
+            subsets = list(itertools.combinations(range(n_mo), n))
+            cB = np.array([abs(np.linalg.det(B[list(I)])) for I in subsets])
+            mats = np.array([orb[e0:e0 + n, 0][:, list(I)] for I in subsets])   # [nI][n][n]
+            D = np.linalg.det(mats)
+            psi *= np.linalg.det(orb[e0:e0 + n, 0, :] @ B)
+            S_spin.append(np.sum(cB * np.abs(D)))
+            g = np.zeros((n, 4))
+            for e in range(n):
+                for q in range(4):
+                    rep = mats.copy()
+                    rep[:, e, :] = orb[e0 + e, 1 + q][np.array(subsets)]
+                    g[e, q] = np.sum(cB * np.abs(np.linalg.det(rep)))
+            G_spin.append(g)
+        s_psi = S_spin[0] * S_spin[1]
+        s_grad = np.concatenate([G_spin[0] * S_spin[1], G_spin[1] * S_spin[0]])
+        assert abs(res.rs_psi[w] - s_psi / abs(psi)) <= 1e-10 * res.rs_psi[w], w
+        np.testing.assert_allclose(res.rs_gl[w], s_grad / abs(psi), rtol=1e-10, atol=0)
 
 
 def test_eq1_equals_bilinear_form():
