@@ -196,13 +196,21 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
                               int32_t *wstatus_dev, void *hip_stream);
 
 /*
- * Reference-conditioning threshold: a (walker, spin) whose reference matrix A
- * has ||A||_1 ||A^-1||_1 above kappa_max (or a zero pivot) is evaluated by the
- * direct-LU fallback instead of the table method.  Default 3e4 -- the
- * analogue of the paper's 1e-3 ratio rule for its update chain (Sec. 2.2):
- * rounding errors of the table method grow with this condition number.
+ * Reference-conditioning threshold of one precision: a (walker, spin) whose
+ * scaled reference matrix A has ||A||_1 ||A^-1||_1 above kappa_max (or a zero
+ * pivot) is evaluated by the direct-LU fallback instead of the table method
+ * -- the analogue of the paper's 1e-3 ratio rule for its update chain
+ * (Sec. 2.2): the rounding error of the table method grows about linearly
+ * with this condition number (about 1e-15 kappa in the scaled error of the
+ * derivatives), so each precision's threshold follows its error bound.
+ *  precision  MDET_FP64, MDET_MIXED, or -1 for both.
+ *  kappa_max  > 0; defaults MDET_KAPPA_FP64_DEFAULT and MDET_KAPPA_MIXED_DEFAULT.
+ * Takes effect at the next evaluation; captured steps (mdet_eval_graph) are
+ * dropped and re-captured.  Errors: MDET_EINVAL.
  */
-mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, double kappa_max);
+#define MDET_KAPPA_FP64_DEFAULT 3e4
+#define MDET_KAPPA_MIXED_DEFAULT 3e4
+mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, int32_t precision, double kappa_max);
 
 /* Evaluation methods of mdet_eval_walkers. */
 enum { MDET_METHOD_TABLE = 0, MDET_METHOD_SM_CHAIN = 1 };

@@ -84,7 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_set_expansion": (I32, [P, I32, I32, I32, I64, P, P, P]),
         "mdet_get_indexing": (I32, [P, P, P, P, P, P, P, P, P, P, P]),
         "mdet_eval_walkers": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
-        "mdet_set_fallback_threshold": (I32, [P, D]),
+        "mdet_set_fallback_threshold": (I32, [P, I32, D]),
         "mdet_get_stats": (I32, [P, P]),
         "mdet_set_profiling": (I32, [P, I32]),
         "mdet_get_kernel_times": (I32, [P, I32, P, P, P, P]),
@@ -187,8 +187,10 @@ class Evaluator:
             self.init_orbitals_dn(wl.pow_abc_dn, wl.alpha_dn, wl.coef_dn)
         self.set_expansion(wl.n_up, wl.n_dn, wl.det_up, wl.det_dn, wl.c, wl.n_int)
 
-    def set_fallback_threshold(self, kappa_max: float):
-        self._check(_LIB.mdet_set_fallback_threshold(self._h, float(kappa_max)))
+    def set_fallback_threshold(self, kappa_max: float, precision: int = -1):
+        """Conditioning threshold of the table method for `precision`
+        (MDET_FP64, MDET_MIXED, or -1 = both)."""
+        self._check(_LIB.mdet_set_fallback_threshold(self._h, int(precision), float(kappa_max)))
 
     def set_method(self, method: int, sm_threshold: float = 1e-3, sm_chunk: int = 64):
         """METHOD_TABLE (default) or METHOD_SM_CHAIN (Sec. 2.2 update chain)."""

@@ -143,7 +143,9 @@ struct mdet_ctx {
         graphs.clear();
     }
     double prep_seconds = 0.0;
-    double kappa_max = 3e4;
+    // reference-conditioning thresholds of the table method, per precision
+    // (index MDET_FP64 / MDET_MIXED)
+    double kappa_max[2] = {MDET_KAPPA_FP64_DEFAULT, MDET_KAPPA_MIXED_DEFAULT};
     // optional per-kernel timing with HIP events (a start and an end event
     // per kernel, on the stream it runs on): a ring of event sets, harvested
     // when the ring wraps or on request
@@ -609,7 +611,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.M = ctx->n_mo;
     a.P = ctx->n_prim;
     a.nmax = std::max(ctx->n_up, ctx->n_dn);
-    a.kappa_max = ctx->kappa_max;
+    a.kappa_max = ctx->kappa_max[precision == MDET_MIXED ? 1 : 0];
     a.prim = ctx->d_prim.as<Prim>();
     a.prim_dn = ctx->two_sets ? ctx->d_prim_dn.as<Prim>() : a.prim;
     for (int s = 0; s < 2; ++s) {
@@ -1136,10 +1138,14 @@ mdet_status mdet_get_kernel_times(mdet_ctx *ctx, int32_t capacity, double *ms_to
     });
 }
 
-mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, double kappa_max) {
+mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, int32_t precision, double kappa_max) {
     return guarded(ctx, [&] {
+        require(precision == MDET_FP64 || precision == MDET_MIXED || precision == -1,
+                MDET_EINVAL, "precision must be MDET_FP64, MDET_MIXED or -1 (both)");
         require(kappa_max > 0.0, MDET_EINVAL, "threshold must be positive");
-        ctx->kappa_max = kappa_max;
+        if (precision != MDET_MIXED) ctx->kappa_max[0] = kappa_max;
+        if (precision != MDET_FP64) ctx->kappa_max[1] = kappa_max;
+        ctx->drop_graphs();  // captured steps hold the threshold by value
     });
 }
 

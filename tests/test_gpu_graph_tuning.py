@@ -80,3 +80,69 @@ def test_autotune_picks_a_valid_config():
     s, l, g, w = gpu_eval(ev, wl.R, precision=1)
     ep, eg = scaled_errors(ref, s, l, g, idx=rows)
     assert ep.max() <= MIXED_TOL and eg.max() <= MIXED_TOL
+
+
+def _graph_eval(ev, R, precision, max_degree=None):
+    Rt = dev(R)
+    md = None if max_degree is None else dev(max_degree, torch.int8)
+    out = ev.eval_graph(Rt, precision=precision, max_degree=md)
+    torch.cuda.synchronize()
+    out = ev.eval_graph(Rt, precision=precision, max_degree=md, out=out)  # a replay
+    torch.cuda.synchronize()
+    return tuple(t.cpu().numpy() for t in out)
+
+
+def test_graph_replay_parity_c3_mixed():
+    """The captured step that the benchmark replays, against the oracle on the
+    full 1e5-product batch in mixed precision (and FP64)."""
+    log("[graph] config 3 replay vs oracle")
+    wl = make_config(3)
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    ref = oracle.evaluate(wl, wl.R, n_threads=16)
+    for prec, tol in ((1, MIXED_TOL), (0, FP64_TOL)):
+        s, l, g, w = _graph_eval(ev, wl.R, prec)
+        ep, eg = scaled_errors(ref, s, l, g)
+        log(f"c3 graph precision {prec}: psi {ep.max():.2e} grad {eg.max():.2e} "
+            f"fallback {np.mean(w == 1):.3f}")
+        assert ep.max() <= tol and eg.max() <= tol, (prec, ep.max(), eg.max())
+
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_graph_replay_parity_c4_uneven(precision, tol):
+    """Uneven batch (per-walker degree limits, walkers sorted by degree inside
+    the captured step) against the oracle on sampled walkers."""
+    log(f"[graph] config 4 replay vs oracle, precision {precision}")
+    wl = make_config(4)
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    s, l, g, w = _graph_eval(ev, wl.R, precision, wl.max_degree)
+    rows = list(range(0, wl.n_walk, wl.n_walk // 48))
+    ref = oracle.evaluate(wl, wl.R[rows], max_degree=wl.max_degree[rows], n_threads=16)
+    ep, eg = scaled_errors(ref, s, l, g, idx=rows)
+    log(f"c4 graph precision {precision}: psi {ep.max():.2e} grad {eg.max():.2e}")
+    assert ep.max() <= tol and eg.max() <= tol
+
+
+def test_threshold_change_reaches_captured_steps():
+    """A new conditioning threshold takes effect on the next replay (the
+    captured step is dropped and captured again)."""
+    log("[graph] threshold change after capture")
+    wl = make_config(2)
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    R = wl.R[:64]
+    s, l, g, w = _graph_eval(ev, R, 0)
+    assert np.mean(w == mdet.W_FALLBACK) < 0.5
+    ev.set_fallback_threshold(1e-300)
+    s, l, g, w = _graph_eval(ev, R, 0)
+    assert np.all(w == mdet.W_FALLBACK)
+    ref = oracle.evaluate(wl, R, n_threads=16)
+    ep, eg = scaled_errors(ref, s, l, g)
+    assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
+    # per precision: only the mixed threshold lowered
+    ev.set_fallback_threshold(3e4, precision=0)
+    s, l, g, w = _graph_eval(ev, R, 0)
+    assert np.mean(w == mdet.W_FALLBACK) < 0.5
+    s, l, g, w = _graph_eval(ev, R, 1)
+    assert np.all(w == mdet.W_FALLBACK)

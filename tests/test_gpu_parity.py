@@ -69,6 +69,10 @@ def test_mixed_parity_c3():
         f"p99 {np.percentile(rel, 99):.2e} max {rel.max():.2e}; quotient-form scaled error "
         f"p50 {np.median(rat):.2e} p99 {np.percentile(rat, 99):.2e} max {rat.max():.2e}")
     assert ep.max() <= MIXED_TOL and eg.max() <= MIXED_TOL
+    # the plain normwise relative error of grad~Psi/Psi: the stated bound holds
+    # for 99 % of walkers; near a node (|Psi| far below the sum of its terms)
+    # FP32 storage of the ratio vectors is amplified by S_Psi/|Psi|
+    assert np.percentile(rel, 99) <= MIXED_TOL and rel.max() <= 10 * MIXED_TOL
 
 
 @pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])

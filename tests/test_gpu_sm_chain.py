@@ -56,9 +56,20 @@ def test_chain_matches_cpu_chain(cid, W):
     for a, b in ((cnt["n_subst"], chain.n_subst), (cnt["n_fail"], chain.n_fail),
                  (cnt["n_inv"] + cnt["n_start"], chain.n_inv)):
         assert abs(a - b) <= 1e-3 * max(b, 1000), (a, b)
-    bar_p = max(FP64_TOL, 10 * cp.max())
-    bar_g = max(FP64_TOL, 10 * cg.max())
-    assert ep.max() <= bar_p and eg.max() <= bar_g
+    # walker by walker against the CPU chain (same decisions, its rounding
+    # differs): within the FP64 bar, or within ten times that walker's own
+    # chain error against the direct LU where the chain amplifies rounding
+    cpu = oracle.Result(chain.sign, chain.logabs, chain.gl, direct.rs_psi, direct.rs_gl)
+    dp, dg = scaled_errors(cpu, sign, logabs, gl)
+    summary(f"c{cid} gpu chain vs cpu chain", dp, dg)
+    assert np.array_equal(np.sign(sign), np.sign(chain.sign))
+    assert np.all(dp <= np.maximum(FP64_TOL, 10 * cp)), np.max(dp / np.maximum(FP64_TOL, 10 * cp))
+    assert np.all(dg <= np.maximum(FP64_TOL, 10 * cg)), np.max(dg / np.maximum(FP64_TOL, 10 * cg))
+    well = (cp <= 1e-12) & (cg <= 1e-12)
+    log(f"walkers where the CPU chain is within 1e-12 of the direct LU: {well.sum()} of {W}; "
+        f"gpu-cpu chain max there: psi {dp[well].max() if well.any() else 0:.2e} "
+        f"grad {dg[well].max() if well.any() else 0:.2e}")
+    assert np.all(dp[well] <= FP64_TOL) and np.all(dg[well] <= FP64_TOL)
 
 
 @pytest.mark.parametrize("cid,W", [(2, 128), (3, 64)])

@@ -144,12 +144,14 @@ def test_mlp_vmc_step_matches_reference(c2):
     np.testing.assert_allclose(Rt.cpu().numpy()[clear], Rnew[clear], rtol=0, atol=1e-5)
 
 
-def test_training_step_gradient_matches_reference(c2):
+@pytest.mark.parametrize("H", [32, 128])
+def test_training_step_gradient_matches_reference(c2, H):
     """Loss and parameter gradient of the ESJD objective vs the exact FP64 one
-    (which the CPU tests pin by finite differences)."""
-    log("[vmc] MLP training step gradient")
+    (which the CPU tests pin by finite differences), at a small width and at
+    the production width 128."""
+    log(f"[vmc] MLP training step gradient, H={H}")
     wl, ev = c2
-    W, N, H = 64, wl.n_elec, 32
+    W, N = 64, wl.n_elec
     p = mlp_init(3 * N, H, 4 * N, seed=12)
     R = wl.R[:W].copy()
     xi = np.random.default_rng(13).normal(size=(W, N, 3))
@@ -174,14 +176,28 @@ def test_training_step_gradient_matches_reference(c2):
     assert np.linalg.norm(g - rg) < 2e-3 * np.linalg.norm(rg)
 
 
-def test_mlp_proposal_samples_the_same_distribution(c2):
+@pytest.mark.parametrize("H,n_train", [(32, 0), (128, 40)])
+def test_mlp_proposal_samples_the_same_distribution(c2, H, n_train):
     """Exactness: <sum r^2> and <E_L> from MLP-proposal VMC agree with
-    Gaussian-proposal VMC within their error bars (untrained network)."""
-    log("[vmc] exactness of the MLP proposal")
+    Gaussian-proposal VMC within their error bars (4 combined standard errors
+    from tau_int), for an untrained network and for a width-128 network after
+    a few library training steps on plain-VMC samples."""
+    log(f"[vmc] exactness of the MLP proposal, H={H}, {n_train} training steps")
     wl, ev = c2
-    N, H = wl.n_elec, 32
-    p = dev(mlp_init(3 * N, H, 4 * N, seed=21), torch.float32)
+    N = wl.n_elec
     R0 = wl.R[:256]
+    p0 = mlp_init(3 * N, H, 4 * N, seed=21)
+    if n_train:
+        w = V.Walkers(ev, R0, seed=30)
+        V.run(w, 100, B.PROP_GAUSSIAN, 0.25, None, record=False)
+        snaps = []
+        for _ in range(8):
+            V.run(w, 5, B.PROP_GAUSSIAN, 0.25, None, record=False)
+            snaps.append(w.R.cpu().numpy())
+        p, losses = V.train_proposal(ev, np.concatenate(snaps), p0, H, n_train, 256, lr=1e-3)
+        log(f"training loss {losses[:5].mean():.4f} -> {losses[-5:].mean():.4f}")
+    else:
+        p = dev(p0, torch.float32)
     stats = {}
     for name, prop, step, mlp_ in (("gauss", B.PROP_GAUSSIAN, 0.25, None),
                                    ("mlp", B.PROP_MLP, 0.0, (p, H))):
@@ -190,8 +206,9 @@ def test_mlp_proposal_samples_the_same_distribution(c2):
         el, r2, acc, _ = V.run(w, 600, prop, step, mlp_)
         stats[name] = (r2, el, acc)
         log(f"{name}: acceptance {acc.mean():.3f}, <sum r^2> {r2.mean():.4f}, <E_L> {np.mean(el):.4f}")
-    for k, idx in (("r2", 0),):
+    for k, idx in (("r2", 0), ("E_L", 1)):
         a, b = stats["gauss"][idx], stats["mlp"][idx]
         ea = a.std() * math.sqrt(V.tau_int(a) / a.size)
         eb = b.std() * math.sqrt(V.tau_int(b) / b.size)
+        log(f"{k}: gauss {a.mean():.4f} +- {ea:.4f}, mlp {b.mean():.4f} +- {eb:.4f}")
         assert abs(a.mean() - b.mean()) < 4.0 * math.hypot(ea, eb), (k, a.mean(), b.mean(), ea, eb)
