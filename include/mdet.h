@@ -196,6 +196,29 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
                               int32_t *wstatus_dev, void *hip_stream);
 
 /*
+ * Allocation-free variant of mdet_eval_walkers, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, outputs, asynchrony,
+ * methods and errors as mdet_eval_walkers; the per-call work buffers come
+ * from a static device array of MDET_NOALLOC_SCRATCH_BYTES per GPU (held by
+ * every GPU the library runs on until the process ends) instead of the
+ * context's grow-only buffers, and the call makes no hipMalloc, hipFree or
+ * other allocating call (no timing events are recorded, and the chain
+ * method's counters are not kept).  The scratch holds the orbital table of
+ * every walker and the ratio and weight vectors of the sparse combination,
+ * about W * (40 N M + 28 (U + V)) bytes; a call that needs more than
+ * MDET_NOALLOC_SCRATCH_BYTES returns MDET_EDIM (with the size in the message)
+ * before queueing anything.  All calls on one GPU share that GPU's array:
+ * every kernel clears what it reads before it is written, but calls that
+ * overlap on one GPU (two streams, two contexts or two threads) race.
+ */
+#define MDET_NOALLOC_SCRATCH_BYTES (64ull << 20)
+mdet_status mdet_eval_walkers_noalloc(mdet_ctx *ctx, int64_t n_walk, const double *R_dev,
+                                      int32_t precision, const int8_t *max_degree_dev,
+                                      double *sign_dev, double *logabs_dev, double *gl_dev,
+                                      int32_t *wstatus_dev, void *hip_stream);
+
+/*
  * Reference-conditioning threshold of one precision: a (walker, spin) whose
  * scaled reference matrix A has ||A||_1 ||A^-1||_1 above kappa_max (or a zero
  * pivot) is evaluated by the direct-LU fallback instead of the table method

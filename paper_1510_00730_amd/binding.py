@@ -33,7 +33,7 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_get_launch_config", "mdet_eval_graph", "mdet_autotune",
             "mdet_norm_truncation", "mdet_set_method", "mdet_get_sm_counters",
             "mdet_set_jastrow", "mdet_dmc_step", "mdet_init_orbitals_dn",
-            "mdet_set_profiling_mask"]
+            "mdet_set_profiling_mask", "mdet_eval_walkers_noalloc"]
 METHOD_TABLE, METHOD_SM_CHAIN = 0, 1
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
 RNG_UNIFORM, RNG_NORMAL = 0, 1
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_set_expansion": (I32, [P, I32, I32, I32, I64, P, P, P]),
         "mdet_get_indexing": (I32, [P, P, P, P, P, P, P, P, P, P, P]),
         "mdet_eval_walkers": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
+        "mdet_eval_walkers_noalloc": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
         "mdet_set_fallback_threshold": (I32, [P, I32, D]),
         "mdet_get_stats": (I32, [P, P]),
         "mdet_set_profiling": (I32, [P, I32]),
@@ -285,6 +286,20 @@ class Evaluator:
         self.eval_raw(W, _dptr(R), precision, _dptr(max_degree), _dptr(sign), _dptr(logabs),
                       _dptr(gl), _dptr(ws), ctypes.c_void_p(stream.cuda_stream))
         return out
+
+    def eval_walkers_noalloc(self, R, sign, logabs, gl, wstatus=None, precision=MDET_FP64,
+                             max_degree=None, stream=None):
+        """The allocation-free evaluation (mdet_eval_walkers_noalloc) into the
+        caller's output tensors; the library's work buffers come from its
+        static device scratch."""
+        import torch
+        W = R.shape[0]
+        if stream is None:
+            stream = torch.cuda.current_stream(R.device)
+        self._check(_LIB.mdet_eval_walkers_noalloc(
+            self._h, int(W), _dptr(R), int(precision), _dptr(max_degree), _dptr(sign),
+            _dptr(logabs), _dptr(gl), _dptr(wstatus), ctypes.c_void_p(stream.cuda_stream)))
+        return sign, logabs, gl, wstatus
 
     # -------------------------------------------------------------- VMC / MLP
     @staticmethod

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmdet.so")
-SOURCES = ["mdet_host.cpp", "mdet_kernels.hip", "mdet_chain.hip", "mdet_vmc.hip", "mdet_dmc.hip"]
+SOURCES = ["mdet_host.cpp", "mdet_kernels.hip", "mdet_chain.hip", "mdet_vmc.hip", "mdet_dmc.hip",
+           "mdet_noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -591,10 +591,75 @@ void ensure_chain(mdet_ctx *c, int64_t W) {
     c->wk.smg32 = c->w_smg.as<float>();
 }
 
+// The work buffers of one evaluation of W walkers carved out of one device
+// region starting at `base` (each piece 256-byte aligned, in a fixed order);
+// returns the bytes the carving needs.  With base == nullptr only the size is
+// computed.  Used by the allocation-free evaluation; the buffers, sizes and
+// uses are those of ensure_work and ensure_chain.
+size_t carve_work(const mdet_ctx *c, int64_t W, char *base, Work &k) {
+    const int M = c->n_mo, N = c->n_up + c->n_dn;
+    const int nmax = std::max(c->n_up, c->n_dn);
+    const int64_t Upad = (c->sp[0].U + 63) / 64 * 64, Vpad = (c->sp[1].U + 63) / 64 * 64;
+    const int64_t RV = Upad + Vpad;
+    const int64_t Wld = (W + 63) / 64 * 64;
+    const int32_t Umax = (int32_t)std::max(c->sp[0].U, c->sp[1].U);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? static_cast<void *>(base + off) : nullptr;
+        off += (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        return p;
+    };
+    k = Work{};
+    k.W = W;
+    k.Wld = Wld;
+    k.M = M;
+    k.N = N;
+    k.nmax = nmax;
+    k.Upad = (int32_t)Upad;
+    k.Vpad = (int32_t)Vpad;
+    k.Umax = Umax;
+    k.phi = (double *)take(sizeof(double) * W * N * 5 * M);
+    k.E = (int32_t *)take(sizeof(int32_t) * W * 2 * M);
+    k.X = (double *)take(sizeof(double) * W * 2 * nmax * nmax);
+    k.g0 = (double *)take(sizeof(double) * W * N * 4);
+    k.logdet0 = (double *)take(sizeof(double) * W * 2);
+    k.sign0 = (double *)take(sizeof(double) * W * 2);
+    k.flag = (int32_t *)take(sizeof(int32_t) * W * 2);
+    k.K = (int32_t *)take(sizeof(int32_t) * W * 2);
+    k.R64 = (double *)take(sizeof(double) * Wld * RV);
+    k.R32 = (float *)take(sizeof(float) * Wld * RV);
+    k.uv64 = (double *)take(sizeof(double) * Wld * RV);
+    k.uv32 = (float *)take(sizeof(float) * Wld * RV);
+    k.psi64 = (double *)take(sizeof(double) * W * kPsiParts);
+    k.Rexp = (int32_t *)take(sizeof(int32_t) * Wld * RV);
+    k.Kmax = (int32_t *)take(sizeof(int32_t) * W * 2);
+    k.dpart = (double *)take(sizeof(double) * W * kDirectSplitMax * N * 4);
+    k.dcount = (int32_t *)take(sizeof(int32_t));
+    k.dlist = (int32_t *)take(sizeof(int32_t) * 2 * W);
+    k.perm = (int32_t *)take(sizeof(int32_t) * W);
+    k.Rs = (double *)take(sizeof(double) * W * N * 3);
+    k.mds = (int8_t *)take(W);
+    k.sign_s = (double *)take(sizeof(double) * W);
+    k.logabs_s = (double *)take(sizeof(double) * W);
+    k.gl_s = (double *)take(sizeof(double) * W * N * 4);
+    k.ws_s = (int32_t *)take(sizeof(int32_t) * W);
+    k.smstat = (unsigned long long *)take(sizeof(unsigned long long) * 4);
+    if (c->method == MDET_METHOD_SM_CHAIN) {
+        void *g = take(sizeof(double) * (size_t)W * 2 * (size_t)Umax * 4 *
+                       (size_t)std::max(1, nmax));
+        k.smg64 = (double *)g;
+        k.smg32 = (float *)g;
+    }
+    return off;
+}
+
 // Queue one evaluation (all kernels) on `st`; arguments already validated.
+// With `fixed` the kernels use those work buffers (nothing is allocated and
+// no timing events are recorded); otherwise the context's grow-only buffers.
 void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
                   const int8_t *max_degree_dev, double *sign_dev, double *logabs_dev,
-                  double *gl_dev, int32_t *wstatus_dev, hipStream_t st) {
+                  double *gl_dev, int32_t *wstatus_dev, hipStream_t st,
+                  const Work *fixed = nullptr) {
     const bool high = ctx->sp[0].high_degree || ctx->sp[1].high_degree;
     if (high && ctx->method != MDET_METHOD_SM_CHAIN)
         throw Status(MDET_EDEGREE, "excitation degree above " + std::to_string(MDET_MAX_DEGREE) +
@@ -602,8 +667,10 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     if (high && max_degree_dev)
         throw Status(MDET_EINVAL, "per-walker degree limits need excitation degrees <= " +
                                       std::to_string(MDET_MAX_DEGREE));
-    ensure_work(ctx, n_walk);
-    ensure_chain(ctx, n_walk);
+    if (!fixed) {
+        ensure_work(ctx, n_walk);
+        ensure_chain(ctx, n_walk);
+    }
     KernelArgs a{};
     a.n_up = ctx->n_up;
     a.n_dn = ctx->n_dn;
@@ -662,8 +729,8 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.method = ctx->method;
     a.sm_threshold = ctx->sm_threshold;
     a.sm_chunk = ctx->sm_chunk;
-    if (a.method == MDET_METHOD_SM_CHAIN) ctx->sm_ran = true;
-    a.wk = ctx->wk;
+    if (a.method == MDET_METHOD_SM_CHAIN && !fixed) ctx->sm_ran = true;  // counters in ctx->wk
+    a.wk = fixed ? *fixed : ctx->wk;
     a.W = n_walk;
     a.R = R_dev;
     a.max_degree = max_degree_dev;
@@ -673,7 +740,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.gl_out = gl_dev;
     a.wstatus = wstatus_dev;
     a.ev_mask = kernels_of_method(a.method) & ctx->prof_user_mask;
-    hipEvent_t *ev = ctx->profiling ? ctx->next_event_set(a.ev_mask) : nullptr;
+    hipEvent_t *ev = (ctx->profiling && !fixed) ? ctx->next_event_set(a.ev_mask) : nullptr;
     HIP_OK(launch_eval(a, st, ev));
     if (ctx->jastrow_on)
         launch_jastrow(n_walk, a.N, a.n_up, ctx->jastrow, R_dev, logabs_dev, gl_dev, st);
@@ -1100,6 +1167,33 @@ mdet_status mdet_eval_walkers(mdet_ctx *ctx, int64_t n_walk, const double *R_dev
         HIP_OK(hipSetDevice(ctx->device));
         enqueue_eval(ctx, n_walk, R_dev, precision, max_degree_dev, sign_dev, logabs_dev, gl_dev,
                      wstatus_dev, static_cast<hipStream_t>(hip_stream));
+    });
+}
+
+mdet_status mdet_eval_walkers_noalloc(mdet_ctx *ctx, int64_t n_walk, const double *R_dev,
+                                      int32_t precision, const int8_t *max_degree_dev,
+                                      double *sign_dev, double *logabs_dev, double *gl_dev,
+                                      int32_t *wstatus_dev, void *hip_stream) {
+    return guarded(ctx, [&] {
+        require(!ctx->host_only, MDET_ESTATE, "host-only context (hip_device -1) cannot evaluate");
+        require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
+        require(n_walk >= 0 && n_walk <= (int64_t)1 << 30, MDET_EDIM, "n_walk out of range");
+        require(precision == MDET_FP64 || precision == MDET_MIXED, MDET_EINVAL, "unknown precision");
+        if (n_walk == 0) return;
+        require(R_dev && sign_dev && logabs_dev && gl_dev, MDET_EINVAL, "null output pointer");
+        Work wk;
+        const size_t need = carve_work(ctx, n_walk, nullptr, wk);
+        if (need > kNoallocBytes)
+            throw Status(MDET_EDIM, "mdet_eval_walkers_noalloc: " + std::to_string(n_walk) +
+                                        " walkers need " + std::to_string(need) +
+                                        " bytes of scratch, more than its " +
+                                        std::to_string(kNoallocBytes) + " bytes");
+        HIP_OK(hipSetDevice(ctx->device));
+        void *base = nullptr;
+        HIP_OK(noalloc_scratch(ctx->device, &base));
+        carve_work(ctx, n_walk, static_cast<char *>(base), wk);
+        enqueue_eval(ctx, n_walk, R_dev, precision, max_degree_dev, sign_dev, logabs_dev, gl_dev,
+                     wstatus_dev, static_cast<hipStream_t>(hip_stream), &wk);
     });
 }
 

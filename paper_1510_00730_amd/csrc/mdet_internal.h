@@ -126,6 +126,13 @@ struct Work {
     unsigned long long *smstat;  // [4] substitutions, recomputations, rejected attempts, chunk starts
 };
 
+// Size of the static device scratch of the allocation-free evaluation
+// (mdet_eval_walkers_noalloc), and the device address of that array on
+// `device` (looked up on the first call, with `device` current; later calls
+// return the same address).
+constexpr size_t kNoallocBytes = (size_t)MDET_NOALLOC_SCRATCH_BYTES;
+hipError_t noalloc_scratch(int device, void **ptr);
+
 // Largest number of blocks per (walker, spin) of the direct-LU fallback.
 constexpr int kDirectSplitMax = 8;
 
