@@ -56,12 +56,15 @@ enum {
 enum { MDET_FP64 = 0, MDET_MIXED = 1 };
 
 /* Largest excitation degree (holes = particles) of a spin determinant relative
- * to the reference spin determinant that the table method evaluates, and the
- * largest per-walker degree limit.  set_expansion accepts any degree; an
- * expansion holding a higher degree is evaluated by MDET_METHOD_SM_CHAIN
- * only (the chain substitutes columns between consecutive determinants and
- * has no degree limit), without per-walker degree limits. */
-#define MDET_MAX_DEGREE 4
+ * to the reference spin determinant that the table method evaluates (the
+ * degree mix of the paper's CIPSI expansions reaches 6-8, Sec. 4, Table 4),
+ * and the largest per-walker degree limit.  Degrees up to 4 have closed-form
+ * or in-register minors; degrees 5-8 take an s x s Gauss-Jordan inversion in
+ * a separate kernel.  set_expansion accepts any degree; an expansion holding
+ * a higher degree is evaluated by MDET_METHOD_SM_CHAIN only (the chain
+ * substitutes columns between consecutive determinants and has no degree
+ * limit), without per-walker degree limits. */
+#define MDET_MAX_DEGREE 8
 /* Largest number of electrons of one spin. */
 #define MDET_MAX_SPIN_ELEC 16
 /* Largest number of orbitals. */
@@ -223,16 +226,18 @@ mdet_status mdet_eval_walkers_noalloc(mdet_ctx *ctx, int64_t n_walk, const doubl
  * scaled reference matrix A has ||A||_1 ||A^-1||_1 above kappa_max (or a zero
  * pivot) is evaluated by the direct-LU fallback instead of the table method
  * -- the analogue of the paper's 1e-3 ratio rule for its update chain
- * (Sec. 2.2): the rounding error of the table method grows about linearly
- * with this condition number (about 1e-15 kappa in the scaled error of the
- * derivatives), so each precision's threshold follows its error bound.
+ * (Sec. 2.2): the rounding error of the table method grows with this
+ * condition number (measured on 4096 walkers of the 1e5-product workload:
+ * scaled derivative error up to 5e-11 below 3e4, 1e-8 to 3e-7 between 3e4
+ * and 1e7, 1e-4 above), so each precision's threshold follows its error
+ * bound (1e-10 in FP64, 1e-5 in mixed precision).
  *  precision  MDET_FP64, MDET_MIXED, or -1 for both.
  *  kappa_max  > 0; defaults MDET_KAPPA_FP64_DEFAULT and MDET_KAPPA_MIXED_DEFAULT.
  * Takes effect at the next evaluation; captured steps (mdet_eval_graph) are
  * dropped and re-captured.  Errors: MDET_EINVAL.
  */
 #define MDET_KAPPA_FP64_DEFAULT 3e4
-#define MDET_KAPPA_MIXED_DEFAULT 3e4
+#define MDET_KAPPA_MIXED_DEFAULT 1e6
 mdet_status mdet_set_fallback_threshold(mdet_ctx *ctx, int32_t precision, double kappa_max);
 
 /* Evaluation methods of mdet_eval_walkers. */
@@ -423,9 +428,13 @@ mdet_status mdet_mlp_adam(mdet_ctx *ctx, int64_t n, float *params, const float *
 /*
  * One training step of the proposal network on walker samples R_dev
  * [W][N][3] with move noise noise_dev [W][N][3]: maximises the expected
- * squared jump distance with the exact acceptance,
- *   loss = -mean_w A_w |R'_w - R_w|^2,  R' = R + mu(R) + sigma(R) xi,
+ * (weighted) squared jump distance with the exact acceptance,
+ *   loss = -mean_w A_w sum_e c_e |r'_e - r_e|^2,  R' = R + mu(R) + sigma(R) xi,
  *   A = min(1, |Psi(R')/Psi(R)|^2 q(R|R')/q(R'|R)),
+ * with c_e = 1 when jump_ref <= 0 (the plain jump distance) and
+ * c_e = 1 / (|r_e|^2 + jump_ref^2) otherwise (each electron's jump relative to
+ * its distance from the nucleus, so that moves of the inner electrons, which
+ * dominate the local energy, weigh as much as those of the outer ones),
  * differentiating through both network evaluations, through ln|Psi(R')|
  * (grad ln|Psi| from the multideterminant path) and through q; then one Adam
  * step (beta 0.9/0.999, eps 1e-8).  loss_dev: double [1]; grad_dev: float
@@ -434,7 +443,8 @@ mdet_status mdet_mlp_adam(mdet_ctx *ctx, int64_t n, float *params, const float *
 mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden, float *params,
                                 float *adam_m, float *adam_v, int32_t t, float lr,
                                 const double *R_dev, const double *noise_dev, int32_t precision,
-                                double *loss_dev, float *grad_dev, void *hip_stream);
+                                double jump_ref, double *loss_dev, float *grad_dev,
+                                void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Launch configuration, captured steps and tuning.
@@ -445,17 +455,23 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
  * sparse combination (0 = derived from the batch, 1..16); direct_split =
  * determinant slices (thread blocks) per flagged (walker, spin) of the
  * direct-LU fallback (0 = one determinant per thread up to 8 slices, 1..8);
- * sort_walkers =
- * with a max_degree array, evaluate the walkers in ascending order of their
- * maximum degree, so that each tile of the sparse combination touches only
- * the determinants its walkers reach.  FP64 results are bitwise reproducible
- * for a fixed configuration (the summation grouping depends on the splits).
- * Default (0, 0, 1).  Changing it drops captured graphs.
+ * sort_walkers = with a max_degree array, evaluate the walkers in ascending
+ * order of their maximum degree, so that each tile of the sparse combination
+ * touches only the determinants its walkers reach; overlap_fallback = run the
+ * direct-LU fallback of the ill-conditioned (walker, spin) pairs on a second
+ * stream of the context, beside the table-method kernels (its ratios beside
+ * the table ratios, its derivative sums beside the derivative aggregation;
+ * joined before the kernels that read them; also inside captured graphs).
+ * FP64 results are bitwise reproducible for a fixed configuration (the
+ * summation grouping depends on the splits; the overlap does not change
+ * results).  Default (0, 0, 1, 1).  Setting it drops captured graphs and the
+ * configurations mdet_autotune remembered.
  */
 mdet_status mdet_set_launch_config(mdet_ctx *ctx, int32_t spmm_row_splits, int32_t direct_split,
-                                   int32_t sort_walkers);
+                                   int32_t sort_walkers, int32_t overlap_fallback);
 mdet_status mdet_get_launch_config(const mdet_ctx *ctx, int32_t *spmm_row_splits,
-                                   int32_t *direct_split, int32_t *sort_walkers);
+                                   int32_t *direct_split, int32_t *sort_walkers,
+                                   int32_t *overlap_fallback);
 
 /*
  * Same contract as mdet_eval_walkers, but the whole step (every kernel) is
@@ -470,16 +486,20 @@ mdet_status mdet_eval_graph(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, 
                             double *gl_dev, int32_t *wstatus_dev, void *hip_stream);
 
 typedef struct {
-    int32_t spmm_row_splits, direct_split, sort_walkers, n_candidates;
+    int32_t spmm_row_splits, direct_split, sort_walkers, overlap_fallback, n_candidates;
     double best_ms;     /* mean time per evaluation of the chosen configuration */
     double default_ms;  /* the same for the first candidate (auto splits)      */
 } mdet_tune_result;
 
 /*
  * Time every candidate launch configuration (row splits {auto, 4, 8, 16} x
- * fallback splits {auto, 2, 4} x walker sorting {on, off} when max_degree_dev
- * is given) on n_rep evaluations of the given walkers, keep the fastest in
- * the context and report it in *out (nullable).  Synchronous.
+ * fallback splits {auto, 2, 4} x fallback overlap {on, off} x walker sorting
+ * {on, off} when max_degree_dev is given) on n_rep evaluations of the given
+ * walkers and report the fastest in *out (nullable).  The context remembers
+ * it for this shape -- (n_walk, precision, with or without per-walker degree
+ * limits), up to 32 shapes -- and later evaluations of that shape use it;
+ * other shapes keep the configuration of mdet_set_launch_config.
+ * Synchronous.
  */
 mdet_status mdet_autotune(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t precision,
                           const int8_t *max_degree_dev, int32_t n_rep, mdet_tune_result *out);

@@ -94,8 +94,9 @@ def log_q(Rb, Ra, mu_a, ls_a):
     return np.sum(-np.sum(d * d, axis=2) / (2.0 * np.exp(2.0 * ls_a)) - 3.0 * ls_a, axis=1)
 
 
-def esjd_loss_and_grad(flat, R, xi, logpsi_R, psi_fn, n_hid):
-    """Loss -mean(A |R'-R|^2) and its exact gradient w.r.t. the parameters.
+def esjd_loss_and_grad(flat, R, xi, logpsi_R, psi_fn, n_hid, jump_ref=0.0):
+    """Loss -mean(A sum_e c_e |r'_e - r_e|^2) and its exact gradient w.r.t.
+    the parameters; c_e = 1, or 1 / (|r_e|^2 + jump_ref^2) when jump_ref > 0.
 
     R [B][N][3], xi [B][N][3]; logpsi_R [B] = ln|Psi(R)|; psi_fn(R') returns
     (ln|Psi(R')| [B], grad ln|Psi(R')| [B][N][3]).  Returns (loss, grad, info).
@@ -116,13 +117,14 @@ def esjd_loss_and_grad(flat, R, xi, logpsi_R, psi_fn, n_hid):
     lq_rev = np.sum(-np.sum(d * d, axis=2) / (2.0 * np.exp(2.0 * ls2)) - 3.0 * ls2, axis=1)
     ell = 2.0 * (lp - logpsi_R) + lq_rev - lq_fwd
     A = np.minimum(1.0, np.exp(np.minimum(ell, 0.0)))
-    jump = np.sum((Rp - R) ** 2, axis=(1, 2))
+    cw = np.ones((B, N)) if jump_ref <= 0 else 1.0 / (np.sum(R * R, axis=2) + jump_ref ** 2)
+    jump = np.sum(cw * np.sum((Rp - R) ** 2, axis=2), axis=1)
     J = A * jump
     loss = -np.mean(J)
     # d loss / d J_w = -1/B
     gJ = -np.ones(B) / B
     g_ell = gJ * np.where(ell < 0.0, A, 0.0) * jump
-    g_Rp = gJ[:, None, None] * A[:, None, None] * 2.0 * (Rp - R)
+    g_Rp = gJ[:, None, None] * A[:, None, None] * 2.0 * cw[:, :, None] * (Rp - R)
     # ell: 2 lnPsi(R') + lq_rev(R', mu2, ls2) - lq_fwd(ls)
     g_Rp += g_ell[:, None, None] * (2.0 * glp + d / s2)
     g_mu2 = g_ell[:, None, None] * (d / s2)

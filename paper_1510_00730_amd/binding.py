@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmdet.so")
 
 MDET_FP64, MDET_MIXED = 0, 1
 W_OK, W_FALLBACK, W_NODE = 0, 1, 2
-MAX_DEGREE = 4
+MAX_DEGREE = 8
 
 STATUS = {0: "MDET_OK", -1: "MDET_EINVAL", -2: "MDET_EDIM", -3: "MDET_EPOPCOUNT",
           -4: "MDET_EORBITAL", -5: "MDET_EDUPLICATE", -6: "MDET_ESPIN", -7: "MDET_ENOMEM",
@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("spmm_row_splits", ctypes.c_int32), ("direct_split", ctypes.c_int32),
-                ("sort_walkers", ctypes.c_int32), ("n_candidates", ctypes.c_int32),
+                ("sort_walkers", ctypes.c_int32), ("overlap_fallback", ctypes.c_int32),
+                ("n_candidates", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("default_ms", ctypes.c_double)]
 
 
@@ -95,9 +96,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_mlp_backward": (I32, [P, I32, I32, I32, P, I64, P, P, P, P, P]),
         "mdet_mlp_adam": (I32, [P, I64, P, P, P, P, I32, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, P]),
-        "mdet_mlp_train_step": (I32, [P, I64, I32, P, P, P, I32, ctypes.c_float, P, P, I32, P, P, P]),
-        "mdet_set_launch_config": (I32, [P, I32, I32, I32]),
-        "mdet_get_launch_config": (I32, [P, P, P, P]),
+        "mdet_mlp_train_step": (I32, [P, I64, I32, P, P, P, I32, ctypes.c_float, P, P, I32, D, P, P,
+                                      P]),
+        "mdet_set_launch_config": (I32, [P, I32, I32, I32, I32]),
+        "mdet_get_launch_config": (I32, [P, P, P, P, P]),
         "mdet_eval_graph": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
         "mdet_autotune": (I32, [P, I64, P, I32, P, I32, P]),
         "mdet_norm_truncation": (I32, [I32, I64, P, P, P, D, D, P, P, P, P]),
@@ -363,22 +365,26 @@ class Evaluator:
                                        self._stream(stream)))
 
     def mlp_train_step(self, params, m, v, t, lr, R, noise, n_hidden, loss, grad=None,
-                       precision=MDET_FP64, stream=None):
+                       precision=MDET_FP64, jump_ref=0.0, stream=None):
+        """One training step (see mdet_mlp_train_step); jump_ref > 0 weighs each
+        electron's squared jump by 1 / (|r_e|^2 + jump_ref^2)."""
         self._check(_LIB.mdet_mlp_train_step(self._h, R.shape[0], int(n_hidden), _dptr(params),
                                              _dptr(m), _dptr(v), int(t), float(lr), _dptr(R),
-                                             _dptr(noise), int(precision), _dptr(loss), _dptr(grad),
-                                             self._stream(stream)))
+                                             _dptr(noise), int(precision), float(jump_ref),
+                                             _dptr(loss), _dptr(grad), self._stream(stream)))
 
     # -------------------------------------------------------------- tuning / graphs
-    def set_launch_config(self, spmm_row_splits=0, direct_split=0, sort_walkers=True):
+    def set_launch_config(self, spmm_row_splits=0, direct_split=0, sort_walkers=True,
+                          overlap_fallback=True):
         self._check(_LIB.mdet_set_launch_config(self._h, int(spmm_row_splits), int(direct_split),
-                                                1 if sort_walkers else 0))
+                                                1 if sort_walkers else 0,
+                                                1 if overlap_fallback else 0))
 
     def launch_config(self):
-        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        a, b, c, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._check(_LIB.mdet_get_launch_config(self._h, ctypes.byref(a), ctypes.byref(b),
-                                                ctypes.byref(c)))
-        return a.value, b.value, bool(c.value)
+                                                ctypes.byref(c), ctypes.byref(d)))
+        return a.value, b.value, bool(c.value), bool(d.value)
 
     def eval_graph(self, R, precision=MDET_FP64, max_degree=None, out=None, stream=None):
         """Like eval_walkers, replaying a captured HIP graph of the whole step."""

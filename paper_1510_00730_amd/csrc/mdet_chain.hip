@@ -338,17 +338,19 @@ __global__ void __launch_bounds__(kBlock) k_sm_scale(KernelArgs a) {
         const size_t o = rv_index(a, sp, d, w);
         const int e = a.wk.Rexp[o];
         const double r = (e == INT_MIN) ? 0.0 : ldexp(a.wk.R64[o], e - K);
+        a.wk.R64[o] = r;
         if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
-        else a.wk.R64[o] = r;
     }
 }
 
 // grad~_e Psi / Psi = sum_d R_d w_d (grad~_e D_d / D_d) / psi with w = u (up)
-// or v (down): one block per (walker, spin); thread t reads component
-// t mod 4n of determinants t / 4n + k (256 / 4n), so each pass reads a
-// contiguous run of the stored ratios.
+// or v (down), the FP64 ratios R_d, and psi = R_up.u, the psi of ln|Psi|
+// (the quotient times the returned Psi is the numerator itself): one block
+// per (walker, spin); thread t
+// reads component t mod 4n of determinants t / 4n + k (256 / 4n), so each
+// pass reads a contiguous run of the stored ratios.
 template <typename F>
-__global__ void __launch_bounds__(kBlock) k_sm_deriv(KernelArgs a, const F *R, const F *uv,
+__global__ void __launch_bounds__(kBlock) k_sm_deriv(KernelArgs a, const double *R, const F *uv,
                                                      const F *smg) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1, tid = threadIdx.x;
     const SpinDev &S = a.sp[sp];
@@ -363,7 +365,7 @@ __global__ void __launch_bounds__(kBlock) k_sm_deriv(KernelArgs a, const F *R, c
         const F *g = smg + ws * (size_t)a.wk.Umax * C4;
         for (int d = tid / cn; d < S.U; d += per) {
             const size_t o = rv_index(a, sp, d, w);
-            s += ((double)R[o] * (double)uv[o]) * (double)g[(size_t)d * C4 + k];
+            s += (R[o] * (double)uv[o]) * (double)g[(size_t)d * C4 + k];
         }
     }
     red[tid] = s;
@@ -371,7 +373,7 @@ __global__ void __launch_bounds__(kBlock) k_sm_deriv(KernelArgs a, const F *R, c
     if (tid < cn) {
         double t = 0.0;
         for (int j = 0; j < per; ++j) t += red[j * cn + tid];
-        const double psi = psi_value(a, w);
+        const double psi = psi_value(a, w, 0);  // the psi of ln|Psi|
         a.gl_out[((size_t)w * a.N + S.e0) * 4 + tid] = t / psi;
     }
 }
@@ -391,7 +393,7 @@ void launch_chain_pieces(const KernelArgs &a, hipStream_t st) {
 void launch_chain_deriv(const KernelArgs &a, hipStream_t st) {
     const dim3 g2(2 * (unsigned)a.W);
     if (a.precision == MDET_MIXED)
-        k_sm_deriv<float><<<g2, dim3(kBlock), 0, st>>>(a, a.wk.R32, a.wk.uv32, a.wk.smg32);
+        k_sm_deriv<float><<<g2, dim3(kBlock), 0, st>>>(a, a.wk.R64, a.wk.uv32, a.wk.smg32);
     else
         k_sm_deriv<double><<<g2, dim3(kBlock), 0, st>>>(a, a.wk.R64, a.wk.uv64, a.wk.smg64);
 }

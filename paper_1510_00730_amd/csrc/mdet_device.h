@@ -19,12 +19,16 @@ __device__ __forceinline__ size_t rv_index(const KernelArgs &a, int sp, int d, i
     return (size_t)w * (size_t)(a.wk.Upad + a.wk.Vpad) + (sp ? (size_t)a.wk.Upad : 0) + d;
 }
 
-// psi of walker w: the row-split partial sums of the sparse combination
-// (accumulated in FP64 in both precisions), added in a fixed order.  All
-// kPsiParts slots are loaded at once (indices clamped to the used ones) so
-// that the loads are in flight together, not one round trip per part.
-__device__ __forceinline__ double psi_value(const KernelArgs &a, int w) {
-    const double *p = a.wk.psi64 + (size_t)w * kPsiParts;
+// psi of walker w formed by spin sp: psi_up = sum_i R_up[i] u[i] (sp 0) or
+// psi_dn = sum_j R_dn[j] v[j] (sp 1), with the FP64 ratios and the stored
+// weights u, v -- equal in exact arithmetic; each matches the derivative
+// aggregate of its spin (same ratios and weights), so that in mixed precision
+// the rounding of the weights is not amplified by a large reference term.
+// The row-split partial sums of the sparse combination are added in a fixed
+// order; all kPsiParts slots are loaded at once (indices clamped to the used
+// ones) so that the loads are in flight together.
+__device__ __forceinline__ double psi_value(const KernelArgs &a, int w, int sp) {
+    const double *p = a.wk.psi64 + ((size_t)w * 2 + sp) * kPsiParts;
     const int np = a.psi_nparts, last = np > 0 ? np - 1 : 0;
     double v[kPsiParts];
 #pragma unroll

@@ -69,6 +69,8 @@ struct SpinHost {
     std::vector<int32_t> exec_of;    // public -> exec
     std::vector<int32_t> pub_of;     // exec -> public
     std::vector<DetDesc> desc;       // exec order
+    std::vector<DetDescHi> desc_hi;  // exec order, degrees kFastDegree+1 .. MDET_MAX_DEGREE
+    std::vector<int32_t> hi_off;     // [n_hi + 1] offsets of their s*s cofactors
     int64_t n_by_degree[MDET_MAX_DEGREE + 1] = {0};
     bool high_degree = false;  // some determinant above MDET_MAX_DEGREE (chain method only)
     int64_t n_above = 0;
@@ -79,14 +81,14 @@ struct SpinHost {
     std::vector<uint16_t> sm_occ;
     std::vector<uint32_t> sm_sub;
     DevBuf d_occ0, d_desc, d_adj_off, d_chunk_det, d_gptr, d_gpos;
-    DevBuf d_sm_exec, d_sm_occ, d_sm_off, d_sm_sub;
-    std::array<DevBuf *, 10> bufs() {
+    DevBuf d_sm_exec, d_sm_occ, d_sm_off, d_sm_sub, d_desc_hi, d_hi_off;
+    std::array<DevBuf *, 12> bufs() {
         return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gptr, &d_gpos,
-                &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub};
+                &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub, &d_desc_hi, &d_hi_off};
     }
-    std::array<const DevBuf *, 10> bufs() const {
+    std::array<const DevBuf *, 12> bufs() const {
         return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gptr, &d_gpos,
-                &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub};
+                &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub, &d_desc_hi, &d_hi_off};
     }
 };
 
@@ -116,7 +118,33 @@ struct mdet_ctx {
     DevBuf d_rptr, d_rcol, d_rval, d_rseg, d_cptr, d_crow, d_cval, d_cseg;
     DevBuf d_rseg32, d_cseg32, d_rdeg, d_cdeg;
     int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
-    LaunchCfg cfg{0, 0, 1};
+    LaunchCfg cfg{0, 0, 1, 1};
+    // configurations found by mdet_autotune, per shape
+    struct TunedShape {
+        int64_t W;
+        int32_t precision, uneven;
+        LaunchCfg cfg;
+    };
+    std::vector<TunedShape> tuned;
+    LaunchCfg cfg_for(int64_t W, int32_t precision, bool uneven) const {
+        for (const auto &t : tuned)
+            if (t.W == W && t.precision == precision && t.uneven == (uneven ? 1 : 0)) return t.cfg;
+        return cfg;
+    }
+    // the fallback's second stream and its fork/join events (created once,
+    // before any capture)
+    AuxStreams aux{nullptr, {nullptr, nullptr, nullptr, nullptr}};
+    void ensure_aux() {
+        if (aux.s) return;
+        HIP_OK(hipStreamCreateWithFlags(&aux.s, hipStreamNonBlocking));
+        for (auto &e : aux.ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    void drop_aux() {
+        for (auto &e : aux.ev)
+            if (e) (void)hipEventDestroy(e);
+        if (aux.s) (void)hipStreamDestroy(aux.s);
+        aux = AuxStreams{nullptr, {nullptr, nullptr, nullptr, nullptr}};
+    }
     int32_t method = MDET_METHOD_TABLE;
     double sm_threshold = 1e-3;
     int32_t sm_chunk = 64;
@@ -192,7 +220,7 @@ struct mdet_ctx {
     int64_t wcap = 0;
     DevBuf w_phi, w_E, w_X, w_g0, w_logdet0, w_sign0, w_flag, w_K, w_R64, w_R32, w_uv64,
         w_uv32, w_psi64, w_Rexp, w_Kmax, w_dpart, w_dcount, w_dlist, w_perm, w_Rs, w_mds, w_sign_s, w_logabs_s, w_gl_s,
-        w_ws_s, w_smstat;
+        w_ws_s, w_smstat, w_adjhi;
     DevBuf w_smg;  // chain method: per-determinant derivative ratios (grown on demand)
     Work wk{};
     // VMC / MLP work buffers (grow-only)
@@ -229,7 +257,7 @@ struct mdet_ctx {
         for (DevBuf *b : {&w_phi, &w_E, &w_X, &w_g0, &w_logdet0, &w_sign0, &w_flag, &w_K,
                           &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp, &w_Kmax, &w_dpart, &w_dcount, &w_dlist,
                           &w_perm, &w_Rs, &w_mds, &w_sign_s, &w_logabs_s, &w_gl_s, &w_ws_s, &w_smstat,
-                          &w_smg})
+                          &w_smg, &w_adjhi})
             b->release();
         sm_ran = false;
         wcap = 0;
@@ -240,7 +268,7 @@ struct mdet_ctx {
         for (const DevBuf *b : {&w_phi, &w_E, &w_X, &w_g0, &w_logdet0, &w_sign0, &w_flag,
                                 &w_K, &w_R64, &w_R32, &w_uv64, &w_uv32, &w_psi64, &w_Rexp,
                                 &w_Kmax, &w_dpart, &w_dcount, &w_dlist, &w_perm, &w_Rs, &w_mds, &w_sign_s,
-                                &w_logabs_s, &w_gl_s, &w_ws_s, &w_smstat, &w_smg})
+                                &w_logabs_s, &w_gl_s, &w_ws_s, &w_smstat, &w_smg, &w_adjhi})
             t += (int64_t)b->bytes;
         return t;
     }
@@ -330,78 +358,106 @@ void validate_spin(const SpinHost &s, int n_int, int n_mo, const char *name) {
 }
 
 // Excitation analysis relative to the reference, execution order by degree,
-// and the lists that aggregate adjugate entries per (slot, orbital) target.
+// and the lists that aggregate cofactor entries per (slot, orbital) target.
 void analyse_spin(SpinHost &s, int n_int, int n_mo) {
     const uint64_t *ref = s.uniq.data() + s.ref * n_int;
     s.occ0 = occupied(ref, n_int);
     const int n = s.n;
-    std::vector<DetDesc> pub_desc(s.U);
-    std::vector<int> deg(s.U);
+    constexpr int DMAX = MDET_MAX_DEGREE;
+    // holes (reference slots, ascending) and particles (orbitals, ascending)
+    // of every distinct determinant; above MDET_MAX_DEGREE only the degree is
+    // kept (such a determinant is evaluated by the chain method only)
+    struct Exc {
+        int s = 0, eps = 1;
+        int h[DMAX] = {0}, p[DMAX] = {0};
+    };
+    std::vector<Exc> pub(s.U);
     std::vector<int32_t> slot_of(n_mo, -1);
     for (int c = 0; c < n; ++c) slot_of[s.occ0[c]] = c;
     for (int64_t i = 0; i < s.U; ++i) {
         const uint64_t *d = s.uniq.data() + i * n_int;
-        DetDesc D;
-        std::memset(&D, 0, sizeof(D));
-        // holes and particles; above MDET_MAX_DEGREE only the degree is kept
-        // (such a determinant is evaluated by the chain method only)
+        Exc &X = pub[i];
         int nh = 0, np = 0;
         for (int c = 0; c < n; ++c) {
             const int m = s.occ0[c];
             if (!((d[m >> 6] >> (m & 63)) & 1ull)) {
-                if (nh < MDET_MAX_DEGREE) D.h[nh] = (uint8_t)c;
+                if (nh < DMAX) X.h[nh] = c;
                 ++nh;
             }
         }
         for (int32_t m : occupied(d, n_int)) {
             if (slot_of[m] < 0) {
-                if (np < MDET_MAX_DEGREE) D.p[np] = (uint16_t)m;
+                if (np < DMAX) X.p[np] = m;
                 ++np;
             }
         }
-        D.s = (uint8_t)nh;
-        if (nh > MDET_MAX_DEGREE) {
+        X.s = nh;
+        if (nh > DMAX) {
             s.high_degree = true;
         } else {
             // sign of the permutation sorting occ0 with h[a] -> p[a] substituted in place
             std::vector<int32_t> lst(s.occ0);
-            for (int a = 0; a < nh; ++a) lst[D.h[a]] = D.p[a];
+            for (int a = 0; a < nh; ++a) lst[X.h[a]] = X.p[a];
             int inv = 0;
             for (int x = 0; x < n; ++x)
                 for (int y = x + 1; y < n; ++y) inv += lst[x] > lst[y];
-            D.eps = (inv & 1) ? -1 : 1;
+            X.eps = (inv & 1) ? -1 : 1;
         }
-        pub_desc[i] = D;
-        deg[i] = nh;
     }
     s.pub_of.resize(s.U);
     std::iota(s.pub_of.begin(), s.pub_of.end(), 0);
     std::stable_sort(s.pub_of.begin(), s.pub_of.end(),
-                     [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+                     [&](int32_t a, int32_t b) { return pub[a].s < pub[b].s; });
     s.exec_of.assign(s.U, 0);
     s.desc.resize(s.U);
-    for (int k = 0; k <= MDET_MAX_DEGREE; ++k) s.n_by_degree[k] = 0;
+    s.desc_hi.clear();
+    s.hi_off.assign(1, 0);
+    for (int k = 0; k <= DMAX; ++k) s.n_by_degree[k] = 0;
     s.n_above = 0;
+    std::vector<Exc> ex(s.U);
     for (int64_t e = 0; e < s.U; ++e) {
         s.exec_of[s.pub_of[e]] = (int32_t)e;
-        s.desc[e] = pub_desc[s.pub_of[e]];
-        if (s.desc[e].s <= MDET_MAX_DEGREE) s.n_by_degree[s.desc[e].s]++;
+        const Exc &X = pub[s.pub_of[e]];
+        ex[e] = X;
+        DetDesc D;
+        std::memset(&D, 0, sizeof(D));
+        D.s = (uint8_t)std::min(X.s, 255);
+        D.eps = (int8_t)X.eps;
+        if (X.s <= kFastDegree) {
+            for (int a = 0; a < X.s; ++a) {
+                D.h[a] = (uint8_t)X.h[a];
+                D.p[a] = (uint16_t)X.p[a];
+            }
+        } else if (X.s <= DMAX) {
+            DetDescHi H;
+            std::memset(&H, 0, sizeof(H));
+            for (int a = 0; a < X.s; ++a) {
+                H.h[a] = (uint8_t)X.h[a];
+                H.p[a] = (uint16_t)X.p[a];
+            }
+            s.desc_hi.push_back(H);
+            s.hi_off.push_back(s.hi_off.back() + X.s * X.s);
+        }
+        s.desc[e] = D;
+        if (X.s <= DMAX) s.n_by_degree[X.s]++;
         else ++s.n_above;
     }
-    if (s.high_degree) {  // no table-method structures: one empty adjugate chunk
+    if (s.high_degree) {  // no table-method structures: one empty cofactor chunk
         s.adj_off.assign(s.U + 1, 0);
         s.chunk_det.assign({0, (int32_t)s.U});
         s.gptr.assign((size_t)n * n_mo + 1, 0);
         s.gpos.assign(1, 0);
+        s.desc_hi.clear();
+        s.hi_off.assign(1, 0);
         return;
     }
-    // Derivative aggregation: the s*s scaled adjugate entries of determinant d
+    // Derivative aggregation: the s*s scaled cofactor entries of determinant d
     // occupy slots adj_off[d] + a*s + b of a staging buffer; determinants are
     // cut into chunks of at most kAdjChunkDets determinants whose slots fit
     // kAdjChunk; per chunk, every target
     // t = h[a]*M + p[b] gets the list of its slots (in determinant order).
     s.adj_off.assign(s.U + 1, 0);
-    for (int64_t e = 0; e < s.U; ++e) s.adj_off[e + 1] = s.adj_off[e] + s.desc[e].s * s.desc[e].s;
+    for (int64_t e = 0; e < s.U; ++e) s.adj_off[e + 1] = s.adj_off[e] + ex[e].s * ex[e].s;
     s.chunk_det.assign(1, 0);
     for (int64_t e = 0; e < s.U; ++e)
         if (s.adj_off[e + 1] - s.adj_off[s.chunk_det.back()] > kAdjChunk ||
@@ -418,19 +474,19 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
         const int32_t base = s.adj_off[s.chunk_det[k]];
         std::vector<int32_t> cnt(nt + 1, 0);
         for (int64_t e = s.chunk_det[k]; e < s.chunk_det[k + 1]; ++e) {
-            const DetDesc &D = s.desc[e];
-            for (int a = 0; a < D.s; ++a)
-                for (int b = 0; b < D.s; ++b) cnt[(int64_t)D.h[a] * n_mo + D.p[b] + 1]++;
+            const Exc &X = ex[e];
+            for (int a = 0; a < X.s; ++a)
+                for (int b = 0; b < X.s; ++b) cnt[(int64_t)X.h[a] * n_mo + X.p[b] + 1]++;
         }
         gp[0] = (int32_t)filled;
         for (int64_t t = 0; t < nt; ++t) gp[t + 1] = gp[t] + cnt[t + 1];
         std::vector<int32_t> fill(gp, gp + nt);
         for (int64_t e = s.chunk_det[k]; e < s.chunk_det[k + 1]; ++e) {
-            const DetDesc &D = s.desc[e];
-            for (int a = 0; a < D.s; ++a)
-                for (int b = 0; b < D.s; ++b) {
-                    const int64_t t = (int64_t)D.h[a] * n_mo + D.p[b];
-                    s.gpos[fill[t]++] = (uint16_t)(s.adj_off[e] - base + a * D.s + b);
+            const Exc &X = ex[e];
+            for (int a = 0; a < X.s; ++a)
+                for (int b = 0; b < X.s; ++b) {
+                    const int64_t t = (int64_t)X.h[a] * n_mo + X.p[b];
+                    s.gpos[fill[t]++] = (uint16_t)(s.adj_off[e] - base + a * X.s + b);
                 }
         }
         filled = gp[nt];
@@ -503,7 +559,17 @@ void require(bool cond, mdet_status code, const char *msg) {
     if (!cond) throw Status(code, msg);
 }
 
+// doubles per (walker, spin) of the cofactors of the determinants of degree
+// above kFastDegree (the larger of the two spins' totals)
+int64_t hi_stride(const mdet_ctx *c) {
+    int64_t h = 0;
+    for (const auto &s : c->sp)
+        if (!s.hi_off.empty()) h = std::max<int64_t>(h, s.hi_off.back());
+    return h;
+}
+
 void ensure_work(mdet_ctx *c, int64_t W) {
+    c->ensure_aux();
     if (W <= c->wcap) return;
     c->drop_work();
     const int M = c->n_mo, N = c->n_up + c->n_dn;
@@ -523,10 +589,12 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     c->w_R32.alloc(sizeof(float) * Wld * RV);
     c->w_uv64.alloc(sizeof(double) * Wld * RV);
     c->w_uv32.alloc(sizeof(float) * Wld * RV);
-    c->w_psi64.alloc(sizeof(double) * W * kPsiParts);
+    c->w_psi64.alloc(sizeof(double) * W * 2 * kPsiParts);
     c->w_Rexp.alloc(sizeof(int32_t) * Wld * RV);
     c->w_Kmax.alloc(sizeof(int32_t) * W * 2);
     c->w_dpart.alloc(sizeof(double) * W * kDirectSplitMax * N * 4);
+    const int64_t hs = hi_stride(c);
+    c->w_adjhi.alloc(sizeof(double) * std::max<int64_t>(1, W * 2 * hs));
     c->w_dcount.alloc(sizeof(int32_t));
     c->w_dlist.alloc(sizeof(int32_t) * 2 * W);
     c->w_perm.alloc(sizeof(int32_t) * W);
@@ -561,6 +629,8 @@ void ensure_work(mdet_ctx *c, int64_t W) {
     k.Rexp = c->w_Rexp.as<int32_t>();
     k.Kmax = c->w_Kmax.as<int32_t>();
     k.dpart = c->w_dpart.as<double>();
+    k.hi_stride = hs;
+    k.adjhi = hs > 0 ? c->w_adjhi.as<double>() : nullptr;
     k.dcount = c->w_dcount.as<int32_t>();
     k.dlist = c->w_dlist.as<int32_t>();
     k.perm = c->w_perm.as<int32_t>();
@@ -630,10 +700,13 @@ size_t carve_work(const mdet_ctx *c, int64_t W, char *base, Work &k) {
     k.R32 = (float *)take(sizeof(float) * Wld * RV);
     k.uv64 = (double *)take(sizeof(double) * Wld * RV);
     k.uv32 = (float *)take(sizeof(float) * Wld * RV);
-    k.psi64 = (double *)take(sizeof(double) * W * kPsiParts);
+    k.psi64 = (double *)take(sizeof(double) * W * 2 * kPsiParts);
     k.Rexp = (int32_t *)take(sizeof(int32_t) * Wld * RV);
     k.Kmax = (int32_t *)take(sizeof(int32_t) * W * 2);
     k.dpart = (double *)take(sizeof(double) * W * kDirectSplitMax * N * 4);
+    k.hi_stride = hi_stride(c);
+    k.adjhi = (double *)take(sizeof(double) * W * 2 * k.hi_stride);
+    if (k.hi_stride == 0) k.adjhi = nullptr;
     k.dcount = (int32_t *)take(sizeof(int32_t));
     k.dlist = (int32_t *)take(sizeof(int32_t) * 2 * W);
     k.perm = (int32_t *)take(sizeof(int32_t) * W);
@@ -697,6 +770,8 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
         }
         d.occ0 = ctx->sp[s].d_occ0.as<int32_t>();
         d.desc = ctx->sp[s].d_desc.as<DetDesc>();
+        d.desc_hi = ctx->sp[s].d_desc_hi.as<DetDescHi>();
+        d.hi_off = ctx->sp[s].d_hi_off.as<int32_t>();
         d.adj_off = ctx->sp[s].d_adj_off.as<int32_t>();
         d.chunk_det = ctx->sp[s].d_chunk_det.as<int32_t>();
         d.gptr = ctx->sp[s].d_gptr.as<int32_t>();
@@ -725,7 +800,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.C.nch_c32 = ctx->nch_c32;
     a.C.rdeg = ctx->d_rdeg.as<int32_t>();
     a.C.cdeg = ctx->d_cdeg.as<int32_t>();
-    a.cfg = ctx->cfg;
+    a.cfg = ctx->cfg_for(n_walk, precision, max_degree_dev != nullptr);
     a.method = ctx->method;
     a.sm_threshold = ctx->sm_threshold;
     a.sm_chunk = ctx->sm_chunk;
@@ -741,7 +816,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.wstatus = wstatus_dev;
     a.ev_mask = kernels_of_method(a.method) & ctx->prof_user_mask;
     hipEvent_t *ev = (ctx->profiling && !fixed) ? ctx->next_event_set(a.ev_mask) : nullptr;
-    HIP_OK(launch_eval(a, st, ev));
+    HIP_OK(launch_eval(a, st, ev, fixed ? nullptr : &ctx->aux));
     if (ctx->jastrow_on)
         launch_jastrow(n_walk, a.N, a.n_up, ctx->jastrow, R_dev, logabs_dev, gl_dev, st);
 }
@@ -851,6 +926,7 @@ void mdet_destroy(mdet_ctx *ctx) {
     ctx->d_prim_dn.release();
     ctx->drop_graphs();
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    ctx->drop_aux();
     ctx->drop_vmc();
     ctx->drop_profile_events();
     delete ctx;
@@ -1021,6 +1097,8 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             sp[s].d_sm_occ.upload(sp[s].sm_occ);
             sp[s].d_sm_off.upload(sp[s].sm_off);
             sp[s].d_sm_sub.upload(sp[s].sm_sub);
+            sp[s].d_desc_hi.upload(sp[s].desc_hi);
+            sp[s].d_hi_off.upload(sp[s].hi_off);
         }
         if (!ctx->host_only) {
             ctx->d_rptr.upload(rptr);
@@ -1049,6 +1127,10 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->sp[s].exec_of.swap(sp[s].exec_of);
             ctx->sp[s].pub_of.swap(sp[s].pub_of);
             ctx->sp[s].desc.swap(sp[s].desc);
+            ctx->sp[s].desc_hi.swap(sp[s].desc_hi);
+            ctx->sp[s].hi_off.swap(sp[s].hi_off);
+            std::swap(ctx->sp[s].d_desc_hi, sp[s].d_desc_hi);
+            std::swap(ctx->sp[s].d_hi_off, sp[s].d_hi_off);
             for (int k = 0; k <= MDET_MAX_DEGREE; ++k) ctx->sp[s].n_by_degree[k] = sp[s].n_by_degree[k];
             ctx->sp[s].high_degree = sp[s].high_degree;
             ctx->sp[s].n_above = sp[s].n_above;
@@ -1482,8 +1564,10 @@ mdet_status mdet_mlp_adam(mdet_ctx *ctx, int64_t n, float *params, const float *
 mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden, float *params,
                                 float *adam_m, float *adam_v, int32_t t, float lr,
                                 const double *R_dev, const double *noise_dev, int32_t precision,
-                                double *loss_dev, float *grad_dev, void *hip_stream) {
+                                double jump_ref, double *loss_dev, float *grad_dev,
+                                void *hip_stream) {
     return guarded(ctx, [&] {
+        require(std::isfinite(jump_ref), MDET_EINVAL, "jump_ref must be finite");
         require(!ctx->host_only, MDET_ESTATE, "host-only context");
         require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
         require(n_walk >= 1 && n_walk <= (int64_t)1 << 24 && n_hidden >= 1 && n_hidden <= 4096,
@@ -1516,7 +1600,7 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
                          ctx->v_signp.as<double>(), ctx->v_logabsp.as<double>(),
                          ctx->v_glp.as<double>(), ctx->m_O1.as<float>(), ctx->m_O2.as<float>(),
                          ctx->m_dO2.as<float>(), ctx->m_gRp.as<double>(), ctx->m_gell.as<double>(),
-                         ctx->m_Jw.as<double>(), st);
+                         ctx->m_Jw.as<double>(), jump_ref, st);
         launch_mlp_backward(sh, params, n_walk, ctx->m_Xp.as<float>(), ctx->m_h1b.as<float>(),
                             ctx->m_h2b.as<float>(), ctx->m_dO2.as<float>(), grad, 0,
                             ctx->m_dX2.as<float>(), ctx->m_wh1.as<float>(), ctx->m_wh2.as<float>(), st);
@@ -1532,24 +1616,28 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
 }
 
 mdet_status mdet_set_launch_config(mdet_ctx *ctx, int32_t spmm_row_splits, int32_t direct_split,
-                                   int32_t sort_walkers) {
+                                   int32_t sort_walkers, int32_t overlap_fallback) {
     return guarded(ctx, [&] {
         require(spmm_row_splits >= 0 && spmm_row_splits <= kPsiParts, MDET_EINVAL,
                 "spmm_row_splits must be 0 (auto) .. 16");
         require(direct_split >= 0 && direct_split <= kDirectSplitMax, MDET_EINVAL,
                 "direct_split must be 0 (auto) .. 8");
-        ctx->cfg = LaunchCfg{spmm_row_splits, direct_split, sort_walkers ? 1 : 0};
+        ctx->cfg = LaunchCfg{spmm_row_splits, direct_split, sort_walkers ? 1 : 0,
+                             overlap_fallback ? 1 : 0};
+        ctx->tuned.clear();
         ctx->drop_graphs();
     });
 }
 
 mdet_status mdet_get_launch_config(const mdet_ctx *cctx, int32_t *spmm_row_splits,
-                                   int32_t *direct_split, int32_t *sort_walkers) {
+                                   int32_t *direct_split, int32_t *sort_walkers,
+                                   int32_t *overlap_fallback) {
     mdet_ctx *ctx = const_cast<mdet_ctx *>(cctx);
     return guarded(ctx, [&] {
         if (spmm_row_splits) *spmm_row_splits = ctx->cfg.spmm_rsplit;
         if (direct_split) *direct_split = ctx->cfg.direct_split;
         if (sort_walkers) *sort_walkers = ctx->cfg.sort_walkers;
+        if (overlap_fallback) *overlap_fallback = ctx->cfg.overlap_fallback;
     });
 }
 
@@ -1654,10 +1742,19 @@ mdet_status mdet_autotune(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, in
             std::vector<LaunchCfg> cand;
             for (int rs : {0, 4, 8, 16})
                 for (int ds : {0, 2, 4})
-                    for (int so : {1, 0}) {
-                        if (!max_degree_dev && so == 0) continue;
-                        cand.push_back(LaunchCfg{rs, ds, so});
-                    }
+                    for (int ov : {1, 0})
+                        for (int so : {1, 0}) {
+                            if (!max_degree_dev && so == 0) continue;
+                            cand.push_back(LaunchCfg{rs, ds, so, ov});
+                        }
+            const bool uneven = max_degree_dev != nullptr;
+            // time the candidates with no remembered configuration for this shape
+            ctx->tuned.erase(std::remove_if(ctx->tuned.begin(), ctx->tuned.end(),
+                                            [&](const mdet_ctx::TunedShape &t) {
+                                                return t.W == n_walk && t.precision == precision &&
+                                                       t.uneven == (uneven ? 1 : 0);
+                                            }),
+                             ctx->tuned.end());
             double best = 1e300, first = 0.0;
             LaunchCfg best_cfg = saved;
             for (size_t c = 0; c < cand.size(); ++c) {
@@ -1679,12 +1776,15 @@ mdet_status mdet_autotune(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, in
                     best_cfg = cand[c];
                 }
             }
-            ctx->cfg = best_cfg;
+            ctx->cfg = saved;
+            if (ctx->tuned.size() >= 32) ctx->tuned.erase(ctx->tuned.begin());
+            ctx->tuned.push_back(mdet_ctx::TunedShape{n_walk, precision, uneven ? 1 : 0, best_cfg});
             ctx->drop_graphs();
             if (out) {
                 out->spmm_row_splits = best_cfg.spmm_rsplit;
                 out->direct_split = best_cfg.direct_split;
                 out->sort_walkers = best_cfg.sort_walkers;
+                out->overlap_fallback = best_cfg.overlap_fallback;
                 out->n_candidates = (int32_t)cand.size();
                 out->best_ms = best;
                 out->default_ms = first;

@@ -33,6 +33,18 @@ struct DetDesc {
 };
 static_assert(sizeof(DetDesc) == 16, "DetDesc layout");
 
+// Degrees up to kFastDegree keep their holes and particles in DetDesc and
+// have closed-form or register minors; a determinant of degree
+// kFastDegree < s <= MDET_MAX_DEGREE keeps them in a DetDescHi (same meaning,
+// up to eight of each), and its s x s minor is inverted by a separate kernel.
+constexpr int kFastDegree = 4;
+struct DetDescHi {
+    uint8_t h[MDET_MAX_DEGREE];
+    uint16_t p[MDET_MAX_DEGREE];
+    uint8_t pad[8];
+};
+static_assert(sizeof(DetDescHi) == 32, "DetDescHi layout");
+
 // Capacity (doubles) of the LDS staging buffer that holds the scaled
 // adjugates of one chunk of determinants during the derivative aggregation.
 constexpr int kAdjChunk = 2048;
@@ -55,6 +67,11 @@ struct SpinDev {
     int32_t deg_end[MDET_MAX_DEGREE + 1];  // execution-order end of degree <= d
     const int32_t *occ0;  // [n] reference occupied orbitals, ascending
     const DetDesc *desc;  // [U] in execution order (ascending degree)
+    // determinants of degree above kFastDegree: execution indices
+    // deg_end[kFastDegree] .. U-1, their holes and particles, and the offset
+    // of each one's s*s cofactors in the (walker, spin) high-degree buffer
+    const DetDescHi *desc_hi;  // [U - deg_end[kFastDegree]]
+    const int32_t *hi_off;     // [U - deg_end[kFastDegree] + 1]
     const int32_t *adj_off;    // [U+1] first adjugate slot of each determinant (sum of s^2)
     const int32_t *chunk_det;  // [nchunk+1] determinant range of each chunk
     const int32_t *gptr;       // [nchunk][n*M+1] per-chunk gather lists, target t = c*M + m
@@ -107,10 +124,16 @@ struct Work {
     float *R32;        // [W][Upad+Vpad]
     double *uv64;      // [W][Upad+Vpad] u (up part) then v (down part)
     float *uv32;       // [W][Upad+Vpad]
-    double *psi64;     // [W][kPsiParts] partial sums of psi (FP64 in both precisions)
+    double *psi64;     // [W][2][kPsiParts] partial sums of psi_up = R_up.u (FP64 ratios)
+                       // and psi_dn = R_dn.v, FP64 in both precisions
+    // R64 holds the shifted FP64 ratios in both precisions (R32 their FP32
+    // copy in mixed precision, the vector the sparse products gather)
     int32_t *Rexp;     // [W][Upad+Vpad] direct-LU fallback: exponents of the determinants
     int32_t *Kmax;     // [W][2] direct-LU fallback: largest exponent (integer max)
     double *dpart;     // [W][kDirectSplitMax][N][4] direct-LU fallback: derivative partial sums
+    int64_t hi_stride; // doubles of the high-degree cofactor buffer per (walker, spin)
+    double *adjhi;     // [W][2][hi_stride] cofactors of the determinants of degree above
+                       // kFastDegree (null when there are none)
     int32_t *dcount;   // [1] direct-LU fallback: number of listed (walker, spin) pairs
     int32_t *dlist;    // [2W] direct-LU fallback: listed pairs, w * 2 + spin (any order)
     // uneven batches: walkers sorted by maximum degree
@@ -142,6 +165,17 @@ struct LaunchCfg {
     int32_t direct_split;  // determinant slices per flagged (walker, spin) of the direct-LU
                            // fallback (0 = one determinant per thread, at most kDirectSplitMax)
     int32_t sort_walkers;  // uneven batches: sort walkers by maximum degree
+    int32_t overlap_fallback;  // run the direct-LU fallback on a second stream, concurrently
+                               // with the table-method kernels (needs AuxStreams)
+};
+
+// A second stream and four events (no timing) owned by the context, for the
+// fallback kernels that run beside the table method: ev[0] after the
+// reference kernel, ev[1] after the fallback ratios, ev[2] after the sparse
+// products, ev[3] after the fallback derivatives.
+struct AuxStreams {
+    hipStream_t s;
+    hipEvent_t ev[4];
 };
 
 // Row splits of the sparse combination per walker tile (partial psi sums).
@@ -180,7 +214,8 @@ uint32_t kernels_of_method(int method);
 // Launch the whole evaluation on `stream`; returns hipSuccess or the first
 // error.  If `events` is not null, events[2k] and events[2k + 1] are recorded
 // on the stream before and after kernel k (k < kNumKernels).
-hipError_t launch_eval(const KernelArgs &a, hipStream_t stream, hipEvent_t *events);
+hipError_t launch_eval(const KernelArgs &a, hipStream_t stream, hipEvent_t *events,
+                       const AuxStreams *aux = nullptr);
 // Sherman-Morrison chain method (its own source file): the chain pieces with
 // the exponent shift, and the derivative sums after the sparse combination.
 void launch_chain_pieces(const KernelArgs &a, hipStream_t stream);
@@ -222,7 +257,7 @@ void launch_mlp_propose(int64_t W, int N, const double *R, const float *o, const
 void launch_esjd_head(int64_t W, int N, const double *R, const double *Rp, const double *xi,
                       const double *logabsR, const double *signp, const double *logabsp,
                       const double *glp, const float *o1, const float *o2, float *dO2,
-                      double *gRp, double *gell, double *Jw, hipStream_t st);
+                      double *gRp, double *gell, double *Jw, double jump_ref, hipStream_t st);
 void launch_esjd_chain(int64_t W, int N, const double *xi, const float *o1, const double *gRp,
                        const float *dX2, const double *gell, float *dO1, hipStream_t st);
 void launch_esjd_loss(int64_t W, const double *Jw, double *out, hipStream_t st);

@@ -357,6 +357,12 @@ __device__ __forceinline__ void stage_adj(const DetDesc &D, const double *T, int
     }
 }
 
+// coef * C_ab of a determinant of degree s > kFastDegree from the cofactors
+// that k_ratios_hi stored (row-major s x s, global memory).
+__device__ __forceinline__ void stage_hi(const double *src, int s, double coef, double *dst) {
+    for (int q = 0; q < s * s; ++q) dst[q] = coef * src[q];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -430,7 +436,6 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
             p_abc[o] = q.a | (q.b << 8) | (q.c << 16);
         }
 
-    if (w == 0 && tid == 0) a.wk.dcount[0] = 0;  // fallback list, filled by k_ratios
     for (int i = tid; i < 2 * M; i += kBlock) {
         emax[i] = INT_MIN;
         slot[i] = -1;
@@ -658,6 +663,133 @@ __device__ __forceinline__ void pair_setup(const double *Xg, const int *Eg, cons
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// K4 for the determinants of degree kFastDegree < s <= MDET_MAX_DEGREE (the
+// higher excitations of the paper's degree mix, Sec. 4, Table 4): one block
+// per (walker, spin) rebuilds T, and each thread inverts whole s x s minors
+// M_d = T[h, p] in registers by pivoted Gauss-Jordan.  It leaves the unshifted
+// ratio eps det M_d and the exponent of its column scales in the ratio
+// vector, the largest exponent in Kmax (k_ratios applies the shift), and the
+// cofactors C_ab = det(M_d) (M_d^-1)_ba in the high-degree buffer for the
+// derivative aggregation.  Runs before k_ratios, for expansions that hold
+// such determinants only.
+// ---------------------------------------------------------------------------
+namespace {
+
+// cofactors of an exactly singular s x s minor (Gauss-Jordan met a zero
+// pivot), each from its (s-1) x (s-1) determinant by pivoted elimination.
+// Out of line: rare, and its registers stay out of the caller.
+__device__ __noinline__ void cofactors_singular(int S, const DetDescHi &H, const double *T, int M,
+                                                double *dst) {
+    for (int r = 0; r < S; ++r)
+        for (int c = 0; c < S; ++c) {
+            double m[(MDET_MAX_DEGREE - 1) * (MDET_MAX_DEGREE - 1)];
+            const int n1 = S - 1;
+            int t = 0;
+            for (int i = 0; i < S; ++i) {
+                if (i == r) continue;
+                for (int j = 0; j < S; ++j)
+                    if (j != c) m[t++] = T[H.h[i] * M + H.p[j]];
+            }
+            double det = 1.0;
+            for (int j = 0; j < n1 && det != 0.0; ++j) {
+                int p = j;
+                for (int i = j + 1; i < n1; ++i)
+                    if (fabs(m[i * n1 + j]) > fabs(m[p * n1 + j])) p = i;
+                if (m[p * n1 + j] == 0.0) {
+                    det = 0.0;
+                    break;
+                }
+                if (p != j) {
+                    for (int k = 0; k < n1; ++k) {
+                        const double x = m[j * n1 + k];
+                        m[j * n1 + k] = m[p * n1 + k];
+                        m[p * n1 + k] = x;
+                    }
+                    det = -det;
+                }
+                det *= m[j * n1 + j];
+                for (int i = j + 1; i < n1; ++i) {
+                    const double l = m[i * n1 + j] / m[j * n1 + j];
+                    for (int k = j + 1; k < n1; ++k) m[i * n1 + k] -= l * m[j * n1 + k];
+                }
+            }
+            dst[r * S + c] = ((r + c) & 1) ? -det : det;
+        }
+}
+
+// ratio eps det M and cofactors C_ab -> dst[a*S + b] of one determinant of
+// compile-time degree S; returns the ratio
+template <int S>
+__device__ __forceinline__ double minor_hi(const DetDescHi &H, int eps, const double *T, int M,
+                                           double *dst) {
+    double m[S][S];
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+#pragma unroll
+        for (int k = 0; k < S; ++k) m[i][k] = T[H.h[i] * M + H.p[k]];
+    double det = 0.0;
+    if (gj_inplace<S>(m, det)) {
+#pragma unroll
+        for (int i = 0; i < S; ++i)
+#pragma unroll
+            for (int k = 0; k < S; ++k) dst[i * S + k] = det * m[k][i];  // C_ab = adj[b][a]
+    } else {
+        det = 0.0;
+        cofactors_singular(S, H, T, M, dst);
+    }
+    return (double)eps * det;
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(kBlock, 1) k_ratios_hi(KernelArgs a) {
+    const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
+    const size_t ws = (size_t)w * 2 + sp;
+    const SpinDev S = a.sp[sp];
+    const int Ulo = S.deg_end[kFastDegree];
+    if (a.wk.flag[ws] != 0 || Ulo >= S.U) return;  // direct-LU fallback, or nothing to do
+    const int n = S.n, M = a.M, tid = threadIdx.x;
+    extern __shared__ double lds[];
+    double *T = lds;                 // [n][M]
+    double *X = T + n * M;           // [n][n]
+    int *Ex = (int *)(X + n * n);    // [M]
+    int *occ0 = Ex + M;              // [n]
+    __shared__ int red[kBlock];
+    const double *phis = a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M;
+    double col0[kMaxN];
+    pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
+               occ0, col0);
+    __syncthreads();
+    build_table(phis, n, M, Ex, X, T, tid, kBlock, col0);
+    __syncthreads();
+    const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
+    double *adj = a.wk.adjhi + ws * a.wk.hi_stride;
+    int kmax = INT_MIN;
+    for (int d = Ulo + tid; d < S.U; d += kBlock) {
+        const DetDesc D = S.desc[d];
+        const DetDescHi H = S.desc_hi[d - Ulo];
+        double *dst = adj + S.hi_off[d - Ulo];
+        const size_t o = rv_index(a, sp, d, w);
+        double r = 0.0;
+        int dx = 0;
+        if (D.s <= dmax) {
+            switch (D.s) {
+            case 5: r = minor_hi<5>(H, D.eps, T, M, dst); break;
+            case 6: r = minor_hi<6>(H, D.eps, T, M, dst); break;
+            case 7: r = minor_hi<7>(H, D.eps, T, M, dst); break;
+            default: r = minor_hi<8>(H, D.eps, T, M, dst); break;
+            }
+            for (int t = 0; t < D.s; ++t) dx += Ex[H.p[t]] - Ex[occ0[H.h[t]]];
+            if (r != 0.0) kmax = max(kmax, expo(r) + dx);
+        }
+        a.wk.R64[o] = r;
+        a.wk.Rexp[o] = dx;  // also for a zero ratio: its cofactors need the scale
+    }
+    const int K = block_max_int(kmax, red);
+    if (tid == 0 && K != INT_MIN) atomicMax(&a.wk.Kmax[ws], K);
+}
+
+// ---------------------------------------------------------------------------
 // K4: ratios R_d / 2^K of every distinct determinant (table method).
 // One block per (walker, spin); one thread per determinant.  Eight waves per
 // SIMD (at most 64 VGPRs) let all pairs of a 1024-walker batch be resident
@@ -666,10 +798,7 @@ __device__ __forceinline__ void pair_setup(const double *Xg, const int *Eg, cons
 __global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
     const int w = blockIdx.x >> 1, sp = blockIdx.x & 1;
     const size_t ws = (size_t)w * 2 + sp;
-    if (a.wk.flag[ws] != 0) {  // ill-conditioned: queue the pair for the direct-LU fallback
-        if (threadIdx.x == 0) a.wk.dlist[atomicAdd(a.wk.dcount, 1)] = (int32_t)ws;
-        return;
-    }
+    if (a.wk.flag[ws] != 0) return;  // ill-conditioned: the direct-LU fallback takes the pair
     const SpinDev S = a.sp[sp];
     const int n = S.n, M = a.M, tid = threadIdx.x;
     extern __shared__ double lds[];
@@ -687,18 +816,22 @@ __global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
     __syncthreads();
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const bool mixed = a.precision == MDET_MIXED;
+    // determinants of degree above kFastDegree (execution indices Ulo..U-1)
+    // were evaluated by k_ratios_hi, which left their unshifted ratios and
+    // exponents and the largest exponent in Kmax
+    const int Ulo = S.deg_end[kFastDegree];
     // the first kKeep determinants of every thread stay in registers until the
     // shift K is known; further ones go through the ratio vector in HBM
     constexpr int kKeep = 4;
     double rk[kKeep];
     int xk[kKeep];
-    int kmax = INT_MIN;
+    int kmax = (tid == 0 && Ulo < S.U) ? a.wk.Kmax[ws] : INT_MIN;
 #pragma unroll
     for (int j = 0; j < kKeep; ++j) {
         const int d = tid + j * kBlock;
         double r = 0.0;
         int dx = 0;
-        if (d < S.U) {
+        if (d < Ulo) {
             const DetDesc D = S.desc[d];
             if (D.s <= dmax) {
                 switch (D.s) {
@@ -714,7 +847,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
         rk[j] = r;
         xk[j] = dx;
     }
-    for (int d = tid + kKeep * kBlock; d < S.U; d += kBlock) {
+    for (int d = tid + kKeep * kBlock; d < Ulo; d += kBlock) {
         const DetDesc D = S.desc[d];
         double r = 0.0;
         if (D.s <= dmax) {
@@ -726,22 +859,29 @@ __global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
     int K = block_max_int(kmax, red);
     if (K == INT_MIN) K = 0;
     if (tid == 0) a.wk.K[ws] = K;
+    for (int d = Ulo + tid; d < S.U; d += kBlock) {  // the high-degree ones
+        const size_t o = rv_index(a, sp, d, w);
+        const int e = a.wk.Rexp[o];
+        const double r = (e == INT_MIN) ? 0.0 : ldexp(a.wk.R64[o], e - K);
+        a.wk.R64[o] = r;
+        if (mixed) a.wk.R32[o] = (float)r;
+    }
 #pragma unroll
     for (int j = 0; j < kKeep; ++j) {
         const int d = tid + j * kBlock;
-        if (d < S.U) {
+        if (d < Ulo) {
             const size_t o = rv_index(a, sp, d, w);
             const double r = ldexp(rk[j], xk[j] - K);
+            a.wk.R64[o] = r;
             if (mixed) a.wk.R32[o] = (float)r;
-            else a.wk.R64[o] = r;
         }
     }
-    for (int d = tid + kKeep * kBlock; d < S.U; d += kBlock) {
+    for (int d = tid + kKeep * kBlock; d < Ulo; d += kBlock) {
         const DetDesc D = S.desc[d];
         const size_t o = rv_index(a, sp, d, w);
         const double r = ldexp(a.wk.R64[o], delta_exponent(D, Ex, occ0) - K);
+        a.wk.R64[o] = r;
         if (mixed) a.wk.R32[o] = (float)r;
-        else a.wk.R64[o] = r;
     }
 }
 
@@ -781,7 +921,8 @@ __device__ __forceinline__ void spmm_block_map(int b, int rsplit, int &tile, int
 
 template <typename F, int CC>
 __global__ void __launch_bounds__(64 * kSpmmWaves)
-    k_spmm(KernelArgs a, const F *__restrict__ R, F *__restrict__ uv,
+    k_spmm(KernelArgs a, const F *__restrict__ R, const double *__restrict__ R64,
+           F *__restrict__ uv,
            const double *__restrict__ rval, const double *__restrict__ cval,
            const int32_t *__restrict__ rcol, const int32_t *__restrict__ crow,
            const int32_t *__restrict__ rseg, const int32_t *__restrict__ cseg, int nch_r, int nch_c,
@@ -910,22 +1051,22 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                 }
                 // u and v are rounded to F here after every chunk; psi takes
                 // the stored value, so it does not depend on how many chunks
-                // the tile needed (walker order in an uneven batch)
+                // the tile needed (walker order in an uneven batch).  Each
+                // pass forms its own psi from the FP64 ratio of its row and
+                // the stored weight: psi_up = R_up.u, psi_dn = R_dn.v
                 const F sf = (F)(s + s2);
                 if (active) uv[o] = sf;
-                if (pass == 0 && (c == nch - 1 || cb + CC >= ncols_eff) && active)
-                    part += (double)R[(size_t)w * RV + i] * (double)sf;
+                if ((c == nch - 1 || cb + CC >= ncols_eff) && active)
+                    part += R64[(size_t)w * RV + ooff + i] * (double)sf;
             }
         }
     }
-    if (pass == 0) {
-        red[wave][lane] = part;
-        __syncthreads();
-        if (wave == 0 && active) {
-            double t = 0.0;
-            for (int g = 0; g < kSpmmWaves; ++g) t += red[g][lane];
-            a.wk.psi64[(size_t)w * kPsiParts + rs] = t;
-        }
+    red[wave][lane] = part;
+    __syncthreads();
+    if (wave == 0 && active) {
+        double t = 0.0;
+        for (int g = 0; g < kSpmmWaves; ++g) t += red[g][lane];
+        a.wk.psi64[((size_t)w * 2 + pass) * kPsiParts + rs] = t;
     }
 }
 
@@ -987,8 +1128,10 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
     DetDesc Dc[kDetsPerThread];
     double wc[kDetsPerThread];
     int oc[kDetsPerThread];
+    int hx[kDetsPerThread];  // degree above kFastDegree: exponent of the column scales
     int gpr[kGpReg];
     uint16_t gqr[kGqReg];
+    const int Ulo = S.deg_end[kFastDegree];
     auto fetch = [&](int k) {
         const int dk = S.chunk_det[k], d1 = S.chunk_det[k + 1];
         const int base = S.adj_off[dk];
@@ -998,12 +1141,14 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
             Dc[j].s = 0;
             wc[j] = 0.0;
             oc[j] = 0;
+            hx[j] = 0;
             if (d < d1) {
                 Dc[j] = S.desc[d];
                 oc[j] = S.adj_off[d] - base;
                 if (Dc[j].s <= dmax) {
                     const size_t o = rv_index(a, sp, d, w);
                     wc[j] = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
+                    if (d >= Ulo) hx[j] = a.wk.Rexp[o];
                 }
             }
         }
@@ -1044,6 +1189,12 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
             const int s = D.s;
             if (s == 0) continue;
             double *dst = cb + oc[j];
+            if (s > kFastDegree) {  // cofactors left by k_ratios_hi
+                const int d = S.chunk_det[k] + tid + j * kBlock;
+                stage_hi(a.wk.adjhi + ws * a.wk.hi_stride + S.hi_off[d - Ulo], s,
+                         (s <= dmax) ? wc[j] * (double)D.eps * pow2(hx[j] - K) : 0.0, dst);
+                continue;
+            }
             const double coef =
                 (s <= dmax) ? wc[j] * (double)D.eps * pow2(delta_exponent(D, Ex, occ0) - K) : 0.0;
             switch (s) {
@@ -1118,13 +1269,20 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
 #pragma unroll
         for (int c = 0; c < kMaxN; ++c) go[c] = Gq[occ0[c < n ? c : n - 1]];
         const double g0 = a.wk.g0[o];
-        const double psi = psi_value(a, w);
+        // the derivative of Psi for this spin's electrons is the numerator
+        // g0 psi_sigma + (s1 - s2): psi_sigma is formed from the same ratios
+        // and weights as the aggregate, so a rounding of the weights cannot
+        // be amplified by a large g0; divided by psi_up, the psi that gives
+        // ln|Psi|, so that the returned ratio times the returned Psi is that
+        // numerator
+        const double psi = psi_value(a, w, 0);
+        const double gr = sp ? g0 * (psi_value(a, w, 1) / psi) : g0;
         double s1 = 0.0, s2 = 0.0;
         for (int g = 0; g < nf; ++g) s1 += scr[tid * nf + g];
 #pragma unroll
         for (int c = 0; c < kMaxN; ++c)
             if (c < n) s2 += (go[c] * pow2(-Ex[occ0[c]])) * Zc[c * n + e];
-        a.gl_out[o] = g0 + (s1 - s2) / psi;
+        a.gl_out[o] = gr + (s1 - s2) / psi;
     }
 }
 
@@ -1210,10 +1368,18 @@ __device__ __forceinline__ void lu_regs(double (&a)[K][K], int (&perm)[K], doubl
 }
 
 // occupied orbital of slot c for determinant D (reference with holes replaced)
-__device__ __forceinline__ int slot_orbital(const DetDesc &D, const int *occ0, int c) {
+// (H: the holes and particles of a determinant of degree above kFastDegree,
+// null otherwise)
+__device__ __forceinline__ int slot_orbital(const DetDesc &D, const DetDescHi *H, const int *occ0,
+                                            int c) {
     int o = occ0[c];
-    for (int t = 0; t < D.s; ++t)
-        if (D.h[t] == c) o = D.p[t];
+    if (H) {
+        for (int t = 0; t < D.s; ++t)
+            if (H->h[t] == c) o = H->p[t];
+    } else {
+        for (int t = 0; t < D.s; ++t)
+            if (D.h[t] == c) o = D.p[t];
+    }
     return o;
 }
 
@@ -1228,13 +1394,13 @@ __device__ __forceinline__ T wave_sum(T v) {
 // with an identity block; occ[c] = orbital of slot c; returns sum of the
 // column exponents.
 template <int K>
-__device__ __forceinline__ int direct_matrix(const DetDesc &D, const int *occ0, const double *P0,
-                                             const int *Ex, int M, int n, double (&A)[K][K],
-                                             int (&occ)[K]) {
+__device__ __forceinline__ int direct_matrix(const DetDesc &D, const DetDescHi *H,
+                                             const int *occ0, const double *P0, const int *Ex,
+                                             int M, int n, double (&A)[K][K], int (&occ)[K]) {
     int sx = 0;
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-        occ[c] = (c < n) ? slot_orbital(D, occ0, c) : 0;
+        occ[c] = (c < n) ? slot_orbital(D, H, occ0, c) : 0;
         if (c < n) sx += Ex[occ[c]];
 #pragma unroll
         for (int e = 0; e < K; ++e) {
@@ -1256,12 +1422,14 @@ __device__ __forceinline__ int direct_ratio_item(const KernelArgs &a, int sp, in
     int kmax = INT_MIN;
     for (int d = d0 + (int)threadIdx.x; d < d1; d += kDirectBlock) {
         const DetDesc D = S.desc[d];
+        const int Ulo = S.deg_end[kFastDegree];
+        const DetDescHi *H = d >= Ulo ? S.desc_hi + (d - Ulo) : nullptr;
         double r = 0.0;
         int rexp = INT_MIN;
         if (D.s <= dmax) {
             double A[K][K];
             int occ[K], perm[K];
-            const int sx = direct_matrix<K>(D, occ0, P0, Ex, M, n, A, occ);
+            const int sx = direct_matrix<K>(D, H, occ0, P0, Ex, M, n, A, occ);
             double mant;
             int ex;
             lu_regs<K, false>(A, perm, mant, ex);
@@ -1297,12 +1465,14 @@ __device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, i
         const int d = base + (int)threadIdx.x;
         const bool in = d < d1;
         const DetDesc D = S.desc[in ? d : d0];
+        const int Ulo = S.deg_end[kFastDegree];
+        const DetDescHi *H = (in ? d : d0) >= Ulo ? S.desc_hi + ((in ? d : d0) - Ulo) : nullptr;
         const size_t o = rv_index(a, sp, in ? d : d0, w);
         const int rexp = a.wk.Rexp[o];
         bool valid = in && D.s <= dmax && rexp != INT_MIN;
         double A[K][K];
         int occ[K], perm[K];
-        direct_matrix<K>(D, occ0, P0, Ex, M, n, A, occ);
+        direct_matrix<K>(D, H, occ0, P0, Ex, M, n, A, occ);
         double mant;
         int ex;
         lu_regs<K, true>(A, perm, mant, ex);
@@ -1395,6 +1565,29 @@ __device__ void stage_orbitals(const KernelArgs &a, int w, int e0, int n, const 
 
 }  // namespace
 
+// the flagged (walker, spin) pairs in ascending order (one block of 1024:
+// per-thread counts over contiguous ranges, a scan, then the writes)
+__global__ void __launch_bounds__(1024) k_direct_list(KernelArgs a) {
+    __shared__ int cnt[1024];
+    const int t = threadIdx.x;
+    const int64_t P = 2 * a.W, per = (P + 1023) / 1024;
+    const int64_t b0 = t * per, b1 = min(P, b0 + per);
+    int c = 0;
+    for (int64_t i = b0; i < b1; ++i) c += a.wk.flag[i] != 0;
+    cnt[t] = c;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // inclusive scan
+        const int v = t >= off ? cnt[t - off] : 0;
+        __syncthreads();
+        cnt[t] += v;
+        __syncthreads();
+    }
+    int pos = cnt[t] - c;
+    for (int64_t i = b0; i < b1; ++i)
+        if (a.wk.flag[i] != 0) a.wk.dlist[pos++] = (int32_t)i;
+    if (t == 1023) a.wk.dcount[0] = cnt[1023];
+}
+
 // pass 1: mantissa and exponent of every determinant of the flagged pairs,
 // and the integer maximum of the exponents per (walker, spin)
 template <int NT>
@@ -1456,8 +1649,8 @@ __global__ void __launch_bounds__(kBlock) k_direct_scale(KernelArgs a) {
             const size_t o = rv_index(a, sp, d, w);
             const int e = a.wk.Rexp[o];
             const double r = (e == INT_MIN) ? 0.0 : ldexp(a.wk.R64[o], e - K);
+            a.wk.R64[o] = r;
             if (a.precision == MDET_MIXED) a.wk.R32[o] = (float)r;
-            else a.wk.R64[o] = r;
         }
     }
 }
@@ -1523,8 +1716,10 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a) {
     if (i >= a.W * per) return;
     const int64_t w = i / per;
     const int t = (int)(i - w * per);
-    const double psi = psi_value(a, (int)w);
-    const bool node = !(psi != 0.0) || !isfinite(psi);
+    // psi_up gives sign and ln|Psi| (and divides every derivative numerator)
+    const double psi = psi_value(a, (int)w, 0);
+    const double psi_dn = psi_value(a, (int)w, 1);
+    const bool node = !(psi != 0.0) || !isfinite(psi) || !(psi_dn != 0.0) || !isfinite(psi_dn);
     const int sp = (t >= 4 * a.sp[1].e0) ? 1 : 0;
     const bool chain = a.method == MDET_METHOD_SM_CHAIN;
     if (node) {
@@ -1539,7 +1734,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(KernelArgs a) {
 #pragma unroll
         for (int p = 0; p < kDirectSplitMax; ++p)
             if (p < np) s += v[p];
-        a.gl_out[i] = s / psi;
+        a.gl_out[i] = s / psi;  // the whole numerator: over the psi of ln|Psi|
     }
     if (t != 0) return;
     if (node) {
@@ -1694,12 +1889,13 @@ int psi_splits(int64_t W, int requested) {
     return std::max(1, std::min(rs, kPsiParts));
 }
 
-hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev);
+hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev, const AuxStreams *aux);
 hipError_t launch_chain(const KernelArgs &a, hipStream_t st, hipEvent_t *ev);
 
 }  // namespace
 
-hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
+hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev,
+                       const AuxStreams *aux) {
     const int64_t W = args.W;
     if (W == 0) return hipSuccess;
     KernelArgs a = args;
@@ -1707,7 +1903,7 @@ hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
     a.direct_split = direct_splits(a, a.cfg.direct_split);
     // stage the orbital derivatives of the fallback in LDS when they fit
     a.direct_stage_grad = sizeof(double) * (5 * (size_t)a.nmax * a.M) <= 96 * 1024 ? 1 : 0;
-    if (!(a.max_degree && a.cfg.sort_walkers)) return launch_core(a, st, ev);
+    if (!(a.max_degree && a.cfg.sort_walkers)) return launch_core(a, st, ev, aux);
     // uneven batch: evaluate the walkers in ascending order of maximum degree
     const int N = a.N;
     k_degree_sort<<<dim3(1), dim3(1024), 0, st>>>(W, a.max_degree, a.wk.perm);
@@ -1720,7 +1916,7 @@ hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
     b.logabs_out = a.wk.logabs_s;
     b.gl_out = a.wk.gl_s;
     b.wstatus = a.wk.ws_s;
-    const hipError_t e = launch_core(b, st, ev);
+    const hipError_t e = launch_core(b, st, ev, aux);
     if (e != hipSuccess) return e;
     k_sort_scatter<<<dim3((unsigned)((W * N * 4 + 255) / 256)), dim3(256), 0, st>>>(
         W, N, a.wk.perm, a.wk.sign_s, a.wk.logabs_s, a.wk.gl_s, a.wk.ws_s, a.sign_out, a.logabs_out,
@@ -1730,54 +1926,93 @@ hipError_t launch_eval(const KernelArgs &args, hipStream_t st, hipEvent_t *ev) {
 
 namespace {
 
-hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
+// The table method.  With `aux` and cfg.overlap_fallback, the direct-LU
+// fallback of the ill-conditioned pairs runs on the second stream: its list
+// and ratios beside the table ratios (joined before the sparse products,
+// which read every ratio), its derivative sums beside the derivative
+// aggregation (joined before the outputs).  Otherwise everything runs in
+// order on `st`.
+hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev, const AuxStreams *aux) {
     const int W = (int)a.W;
     const int n = a.nmax, M = a.M;
     const dim3 g2(2 * W), blk(kBlock);
-    auto mark = [&](int k, bool end) {
-        if (ev && ((a.ev_mask >> k) & 1u)) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], st);
+    const bool ovl = aux && a.cfg.overlap_fallback && a.method != MDET_METHOD_SM_CHAIN;
+    hipStream_t sf = ovl ? aux->s : st;  // the fallback's stream
+    auto mark = [&](int k, bool end, hipStream_t s) {
+        if (ev && ((a.ev_mask >> k) & 1u)) (void)hipEventRecord(ev[2 * k + (end ? 1 : 0)], s);
     };
-    mark(0, false);
+    hipError_t err = hipSuccess;
+    auto fork = [&](hipEvent_t e, hipStream_t from, hipStream_t to) {
+        if (err == hipSuccess) err = hipEventRecord(e, from);
+        if (err == hipSuccess) err = hipStreamWaitEvent(to, e, 0);
+    };
+    mark(0, false, st);
     const size_t prim_bytes = (size_t)(a.prim_dn != a.prim ? 2 : 1) * M * a.P * kPrimLdsBytes;
     const size_t lds_ref = sizeof(double) * (14 * (size_t)n * n + 2 * (2 * kMaxN + 2) +
                                              (size_t)a.N * (3 * kPowLd + 1)) +
                            sizeof(int) * (4 * (size_t)M + 2 * kMaxN) +
                            (prim_bytes <= kPrimLdsMax ? prim_bytes : 0);
     k_reference<<<dim3(W), blk, lds_ref, st>>>(a);
-    mark(0, true);
+    mark(0, true, st);
     if (a.method == MDET_METHOD_SM_CHAIN) return launch_chain(a, st, ev);
-    mark(1, false);
+    const unsigned gscale = (unsigned)std::min<int64_t>(2 * (int64_t)W * a.direct_split, 1024);
+    auto fallback_ratios = [&]() {
+        mark(2, false, sf);
+        k_direct_list<<<dim3(1), dim3(1024), 0, sf>>>(a);
+        launch_direct_n(a, sf, false);
+        k_direct_scale<<<dim3(gscale), blk, 0, sf>>>(a);
+        mark(2, true, sf);
+    };
+    if (ovl) {
+        fork(aux->ev[0], st, sf);
+        fallback_ratios();
+        if (err == hipSuccess) err = hipEventRecord(aux->ev[1], sf);
+    }
+    mark(1, false, st);
     const size_t lds_rat = sizeof(double) * ((size_t)n * M + n * n) + sizeof(int) * (M + n);
+    if (a.wk.hi_stride > 0) k_ratios_hi<<<g2, blk, lds_rat, st>>>(a);
     k_ratios<<<g2, blk, lds_rat, st>>>(a);
-    mark(1, true);
-    mark(2, false);
-    launch_direct_n(a, st, false);
-    k_direct_scale<<<dim3((unsigned)std::min<int64_t>(2 * (int64_t)W * a.direct_split, 1024)),
-                     blk, 0, st>>>(a);
-    mark(2, true);
-    mark(3, false);
+    mark(1, true, st);
+    if (ovl) {
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, aux->ev[1], 0);
+    } else {
+        fallback_ratios();
+    }
+    mark(3, false, st);
     const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
     const dim3 gs((tiles + 7) / 8 * 8 * a.psi_nparts, 2), bs(64 * kSpmmWaves);
     if (a.precision == MDET_MIXED)
         k_spmm<float, kSpmmCols32><<<gs, bs, 0, st>>>(
-            a, a.wk.R32, a.wk.uv32, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg32,
+            a, a.wk.R32, a.wk.R64, a.wk.uv32, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg32,
             a.C.cseg32, a.C.nch_r32, a.C.nch_c32, a.psi_nparts);
     else
         k_spmm<double, kSpmmCols64><<<gs, bs, 0, st>>>(
-            a, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
+            a, a.wk.R64, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
             a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
-    mark(3, true);
-    mark(4, false);
+    mark(3, true, st);
+    if (ovl) {
+        fork(aux->ev[2], st, sf);
+        mark(5, false, sf);
+        launch_direct_n(a, sf, true);
+        mark(5, true, sf);
+        if (err == hipSuccess) err = hipEventRecord(aux->ev[3], sf);
+    }
+    mark(4, false, st);
     const size_t lds_der = sizeof(double) * (2 * (size_t)n * M + n * n + deriv_union_doubles(n, M)) +
                            sizeof(int) * (M + n);
     k_deriv<<<g2, blk, lds_der, st>>>(a);
-    mark(4, true);
-    mark(5, false);
-    launch_direct_n(a, st, true);
-    mark(5, true);
-    mark(6, false);
+    mark(4, true, st);
+    if (ovl) {
+        if (err == hipSuccess) err = hipStreamWaitEvent(st, aux->ev[3], 0);
+    } else {
+        mark(5, false, st);
+        launch_direct_n(a, st, true);
+        mark(5, true, st);
+    }
+    mark(6, false, st);
     k_finalize<<<dim3((unsigned)(((int64_t)W * 4 * a.N + kBlock - 1) / kBlock)), blk, 0, st>>>(a);
-    mark(6, true);
+    mark(6, true, st);
+    if (err != hipSuccess) return err;
     return hipGetLastError();
 }
 
@@ -1798,11 +2033,11 @@ hipError_t launch_chain(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     const dim3 gs((tiles + 7) / 8 * 8 * a.psi_nparts, 2), bs(64 * kSpmmWaves);
     if (mixed)
         k_spmm<float, kSpmmCols32><<<gs, bs, 0, st>>>(
-            a, a.wk.R32, a.wk.uv32, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg32,
+            a, a.wk.R32, a.wk.R64, a.wk.uv32, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg32,
             a.C.cseg32, a.C.nch_r32, a.C.nch_c32, a.psi_nparts);
     else
         k_spmm<double, kSpmmCols64><<<gs, bs, 0, st>>>(
-            a, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
+            a, a.wk.R64, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
             a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
     mark(3, true);
     mark(8, false);

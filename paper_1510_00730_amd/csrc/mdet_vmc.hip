@@ -233,15 +233,22 @@ __global__ void __launch_bounds__(kVBlock) k_mlp_propose(int64_t W, int N, const
     Rp[t] = R[t] + (double)ow[r] + exp(ls) * xi[t];
 }
 
-// Per-walker part of the training objective J = A |R'-R|^2 (loss = -mean J):
-// writes the output gradient of the evaluation at R' (dO2, FP32), the direct
-// gradient w.r.t. R' (gRp, FP64), g_ell and the walker's J.
+// weight of electron e's squared jump: 1, or 1 / (|r_e|^2 + jref^2)
+__device__ __forceinline__ double jump_weight(const double *r, double jref) {
+    return jref > 0.0 ? 1.0 / (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + jref * jref) : 1.0;
+}
+
+// Per-walker part of the training objective J = A sum_e c_e |r'_e - r_e|^2
+// (loss = -mean J, c_e = jump_weight): writes the output gradient of the
+// evaluation at R' (dO2, FP32), the direct gradient w.r.t. R' (gRp, FP64),
+// g_ell and the walker's J.
 __global__ void __launch_bounds__(kVBlock) k_esjd_head(int64_t W, int N, const double *R,
                                                        const double *Rp, const double *xi,
                                                        const double *logabsR, const double *signp,
                                                        const double *logabsp, const double *glp,
                                                        const float *o1, const float *o2, float *dO2,
-                                                       double *gRp, double *gell, double *Jw) {
+                                                       double *gRp, double *gell, double *Jw,
+                                                       double jref) {
     const int64_t w = (int64_t)blockIdx.x * kVBlock + threadIdx.x;
     if (w >= W) return;
     const int n3 = 3 * N, n4 = 4 * N;
@@ -252,14 +259,15 @@ __global__ void __launch_bounds__(kVBlock) k_esjd_head(int64_t W, int N, const d
         const double ls = fmin(fmax((double)a1[n3 + e], kMlpLogSigMin), kMlpLogSigMax);
         const double ls2 = fmin(fmax((double)a2[n3 + e], kMlpLogSigMin), kMlpLogSigMax);
         const double inv2 = exp(-2.0 * ls2);
-        double x2 = 0.0, d2 = 0.0;
+        double x2 = 0.0, d2 = 0.0, j2 = 0.0;
         for (int ax = 0; ax < 3; ++ax) {
             x2 += xw[3 * e + ax] * xw[3 * e + ax];
             const double d = Rw[3 * e + ax] - Rpw[3 * e + ax] - (double)a2[3 * e + ax];
             d2 += d * d;
             const double j = Rpw[3 * e + ax] - Rw[3 * e + ax];
-            jump += j * j;
+            j2 += j * j;
         }
+        jump += jump_weight(Rw + 3 * e, jref) * j2;
         lq_fwd += -0.5 * x2 - 3.0 * ls;
         lq_rev += -0.5 * d2 * inv2 - 3.0 * ls2;
     }
@@ -275,11 +283,12 @@ __global__ void __launch_bounds__(kVBlock) k_esjd_head(int64_t W, int N, const d
         const double ls2 = fmin(fmax(raw2, kMlpLogSigMin), kMlpLogSigMax);
         const bool in2 = raw2 > kMlpLogSigMin && raw2 < kMlpLogSigMax;
         const double inv2 = exp(-2.0 * ls2);
+        const double ce = jump_weight(Rw + 3 * e, jref);
         double d2 = 0.0;
         for (int ax = 0; ax < 3; ++ax) {
             const double d = Rw[3 * e + ax] - Rpw[3 * e + ax] - (double)a2[3 * e + ax];
             d2 += d * d;
-            const double g = gJ * A * 2.0 * (Rpw[3 * e + ax] - Rw[3 * e + ax]) +
+            const double g = gJ * A * 2.0 * ce * (Rpw[3 * e + ax] - Rw[3 * e + ax]) +
                              ge * (2.0 * glp[w * n4 + 4 * e + ax] + d * inv2);
             gRp[w * n3 + 3 * e + ax] = g;
             dO2[w * n4 + 3 * e + ax] = (float)(ge * d * inv2);
@@ -439,9 +448,9 @@ void launch_mlp_propose(int64_t W, int N, const double *R, const float *o, const
 void launch_esjd_head(int64_t W, int N, const double *R, const double *Rp, const double *xi,
                       const double *logabsR, const double *signp, const double *logabsp,
                       const double *glp, const float *o1, const float *o2, float *dO2,
-                      double *gRp, double *gell, double *Jw, hipStream_t st) {
+                      double *gRp, double *gell, double *Jw, double jump_ref, hipStream_t st) {
     k_esjd_head<<<g1(W), dim3(kVBlock), 0, st>>>(W, N, R, Rp, xi, logabsR, signp, logabsp, glp, o1,
-                                                  o2, dO2, gRp, gell, Jw);
+                                                  o2, dO2, gRp, gell, Jw, jump_ref);
 }
 
 void launch_esjd_chain(int64_t W, int N, const double *xi, const float *o1, const double *gRp,

@@ -5,11 +5,16 @@
    by the expected squared jump distance (ESJD).
 2. About 1e6 walker configurations are sampled from that chain (thinned).
 3. The MLP proposal (51 -> 128 -> 128 -> 68, tanh, FP32) is trained on them
-   with the library's training step (ESJD with the exact acceptance).
-4. Both proposals run from the same equilibrated walkers; reported per
-   proposal: acceptance, ESJD, integrated autocorrelation time of the
-   walker-averaged local energy and of sum r^2, wall time per step, and
-   effective samples per second = walkers * steps / time / tau_int.
+   with the library's training step (jump objective with the exact
+   acceptance), once per jump weighting: the plain squared jump, and the
+   jump of each electron relative to its distance from the nucleus
+   (weights 1 / (r^2 + ref^2)), which counts the moves of the inner
+   electrons that dominate the local energy.
+4. Every proposal runs from the same equilibrated walkers -- the Gaussian at
+   every step of the grid, so that the best Gaussian for the local energy is
+   the baseline -- reporting acceptance, ESJD, integrated autocorrelation
+   time of the walker-averaged local energy and of sum r^2, wall time per
+   step, and effective samples per second = walkers * steps / time / tau_int.
 
 Run: python -m paper_1510_00730_amd.learned_proposal [--quick]
 Prints one JSON object.
@@ -44,6 +49,8 @@ def main(argv=None):
     ap.add_argument("--train-iters", type=int, default=1500)
     ap.add_argument("--compare-steps", type=int, default=2000)
     ap.add_argument("--config", type=int, default=5)
+    ap.add_argument("--jump-refs", type=float, nargs="+", default=[0.0, 1.0, 0.3],
+                    help="jump weightings to train (0: plain squared jump)")
     args = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
@@ -69,7 +76,8 @@ def main(argv=None):
     w = Walkers(ev, wl.R, seed=101)
     run(w, 150 if not args.quick else 60, PROP_GAUSSIAN, 0.2, record=False)
     best = None
-    for s in (0.1, 0.15, 0.2, 0.3, 0.45):
+    grid = (0.1, 0.15, 0.2, 0.3, 0.45)
+    for s in grid:
         e = esjd_of(w, run, 40 if not args.quick else 15, PROP_GAUSSIAN, s)
         if best is None or e > best[1]:
             best = (s, e)
@@ -83,32 +91,51 @@ def main(argv=None):
         snaps.append(w.R.float().cpu().numpy())
     samples = np.concatenate(snaps).astype(np.float64)
     out["training_samples"] = int(samples.shape[0])
-    # 3. training
+    # 3. training, one network per jump weighting
     p0 = mlp_init(3 * N, H, 4 * N, seed=7)
-    t0 = time.perf_counter()
-    params, losses = train_proposal(ev, samples, p0, H, args.train_iters, min(2048, W), lr=1e-3)
-    out["train_seconds"] = time.perf_counter() - t0
-    out["train_loss_first_last"] = [float(np.mean(losses[:20])), float(np.mean(losses[-20:]))]
+    nets = {}
+    for ref in args.jump_refs:
+        t0 = time.perf_counter()
+        params, losses = train_proposal(ev, samples, p0, H, args.train_iters, min(2048, W),
+                                        lr=1e-3, jump_ref=ref)
+        nets[ref] = params
+        out.setdefault("training", {})[f"jump_ref={ref:g}"] = {
+            "seconds": time.perf_counter() - t0,
+            "loss_first_last": [float(np.mean(losses[:20])), float(np.mean(losses[-20:]))]}
     # 4. comparison from the same equilibrated walkers
     R_eq = w.R.cpu().numpy()
     res = {}
-    for name, prop, stp, mlp in (("gaussian", PROP_GAUSSIAN, step, None),
-                                 ("mlp", PROP_MLP, 0.0, (params, H))):
+    runs = [(f"gaussian_step={s:g}", PROP_GAUSSIAN, s, None) for s in grid]
+    runs += [(f"mlp_jump_ref={ref:g}", PROP_MLP, 0.0, (nets[ref], H)) for ref in args.jump_refs]
+    for name, prop, stp, mlp in runs:
         wk = Walkers(ev, R_eq, seed=202)
         run(wk, 50, prop, stp, mlp, record=False)
         jd = esjd_of(wk, run, 50, prop, stp, mlp)
         el, r2, acc, dt = run(wk, args.compare_steps, prop, stp, mlp)
         t_el, t_r2 = tau_int(el), tau_int(r2)
         rate = W * args.compare_steps / dt
-        res[name] = {"acceptance": float(acc.mean()), "esjd": jd, "ms_per_step": 1e3 * dt / args.compare_steps,
+        res[name] = {"acceptance": float(acc.mean()), "esjd": jd,
+                     "ms_per_step": 1e3 * dt / args.compare_steps,
                      "tau_int_E_L": t_el, "tau_int_sum_r2": t_r2, "mean_E_L": float(np.mean(el)),
+                     "err_E_L": float(np.std(el) * np.sqrt(t_el / el.size)),
                      "mean_sum_r2": float(np.mean(r2)),
                      "effective_samples_per_s_E_L": rate / t_el,
                      "effective_samples_per_s_sum_r2": rate / t_r2}
+        print(f"[proposal] {name}: {res[name]}", file=sys.stderr, flush=True)
     out["proposals"] = res
-    g, m = res["gaussian"], res["mlp"]
-    out["gain_E_L"] = m["effective_samples_per_s_E_L"] / g["effective_samples_per_s_E_L"]
-    out["gain_sum_r2"] = m["effective_samples_per_s_sum_r2"] / g["effective_samples_per_s_sum_r2"]
+    gauss = {k: v for k, v in res.items() if k.startswith("gaussian")}
+    best_g = max(gauss, key=lambda k: gauss[k]["effective_samples_per_s_E_L"])
+    esjd_g = f"gaussian_step={step:g}"
+    out["baseline_best_gaussian_E_L"] = best_g
+    out["gain_E_L_vs_best_gaussian"] = {
+        k: v["effective_samples_per_s_E_L"] / gauss[best_g]["effective_samples_per_s_E_L"]
+        for k, v in res.items() if k.startswith("mlp")}
+    out["gain_E_L_vs_esjd_tuned_gaussian"] = {
+        k: v["effective_samples_per_s_E_L"] / gauss[esjd_g]["effective_samples_per_s_E_L"]
+        for k, v in res.items() if k.startswith("mlp")}
+    out["gain_sum_r2_vs_esjd_tuned_gaussian"] = {
+        k: v["effective_samples_per_s_sum_r2"] / gauss[esjd_g]["effective_samples_per_s_sum_r2"]
+        for k, v in res.items() if k.startswith("mlp")}
     out["total_seconds"] = time.perf_counter() - t_start
     print(json.dumps(out), flush=True)
     ev.close()

@@ -89,9 +89,10 @@ def tau_int(x, c=5.0):
 
 
 def train_proposal(ev: Evaluator, samples, params0, n_hidden, n_iter, batch, lr=1e-3, seed=5,
-                   precision=MDET_FP64, log_every=0):
+                   precision=MDET_FP64, log_every=0, jump_ref=0.0):
     """Train the MLP proposal on `samples` [S][N][3] (host), `n_iter` library
-    training steps on random batches.  Returns (params tensor, losses)."""
+    training steps on random batches (jump_ref: the jump weighting of
+    mdet_mlp_train_step).  Returns (params tensor, losses)."""
     import torch
     p = torch.as_tensor(params0, dtype=torch.float32, device="cuda").clone()
     m = torch.zeros_like(p)
@@ -107,7 +108,8 @@ def train_proposal(ev: Evaluator, samples, params0, n_hidden, n_iter, batch, lr=
         idx = torch.as_tensor(rng.integers(0, S, batch), device="cuda")
         Rb.copy_(dev_samples.index_select(0, idx))
         ev.rng_fill(noise, seed, TRAIN_STREAM, t, RNG_NORMAL)
-        ev.mlp_train_step(p, m, v, t, lr, Rb, noise, n_hidden, loss, precision=precision)
+        ev.mlp_train_step(p, m, v, t, lr, Rb, noise, n_hidden, loss, precision=precision,
+                          jump_ref=jump_ref)
         losses.append(loss.clone())
         if log_every and t % log_every == 0:
             print(f"[train] iter {t} loss {float(loss):.5f}", flush=True)

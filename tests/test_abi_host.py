@@ -128,10 +128,19 @@ def test_error_codes():
     dup_d = np.concatenate([wl.det_dn, wl.det_dn[7:8]])
     _expect(-5, lambda: ev.set_expansion(5, 5, dup_u, dup_d, np.append(wl.c, 0.01)))  # EDUPLICATE
     far = encode([[15, 16, 17, 18, 19]], 1)                                    # degree 5 from ref
-    # accepted (the chain method evaluates it); the degree shows in the counts
+    # a degree above 4 is a table-method degree (s x s minors up to 8 x 8)
     ev.set_expansion(5, 5, np.concatenate([wl.det_up, far]),
                      np.concatenate([wl.det_dn, wl.det_dn[:1]]), np.append(wl.c, 0.001))
     st = ev.stats()
+    assert sum(st.n_by_degree_up) == st.n_uniq_up and st.n_by_degree_up[5] == 1
+    # degree 9 (above MDET_MAX_DEGREE): accepted for the chain method, outside the counts
+    ev10 = mdet.Evaluator(device=-1)
+    ev10.init_orbitals(np.zeros((20, 1, 3), np.int32), np.full((20, 1), 0.5), np.ones((20, 1)))
+    ref10 = list(range(10))
+    up = encode([ref10, [0] + list(range(11, 20))], 1)
+    dn = encode([list(range(9)), list(range(9))], 1)
+    ev10.set_expansion(10, 9, up, dn, np.array([0.9, 0.1]))
+    st = ev10.stats()
     assert sum(st.n_by_degree_up) == st.n_uniq_up - 1
     ev.set_expansion(5, 5, wl.det_up, wl.det_dn, wl.c)                         # still usable
     _expect(-9, lambda: ev.eval_raw(1, None, 0, None, None, None, None, None, None))

@@ -50,10 +50,13 @@ def test_walker_sorting_is_bitwise_neutral_and_configs_pass_parity():
     res = {}
     for prec in (0, 1):
         for sort in (True, False):
-            ev.set_launch_config(0, 4, sort)
-            res[(prec, sort)] = [t.cpu() for t in ev.eval_walkers(R, precision=prec, max_degree=md)]
-        for a, b in zip(res[(prec, True)], res[(prec, False)]):
-            assert torch.equal(a, b)
+            for ovl in (True, False):
+                ev.set_launch_config(0, 4, sort, ovl)
+                res[(prec, sort, ovl)] = [t.cpu() for t in
+                                          ev.eval_walkers(R, precision=prec, max_degree=md)]
+        for key in ((prec, True, False), (prec, False, True), (prec, False, False)):
+            for a, b in zip(res[(prec, True, True)], res[key]):
+                assert torch.equal(a, b), key
     rows = list(range(0, 512, 16))
     ref = oracle.evaluate(wl, wl.R[rows], max_degree=wl.max_degree[rows], n_threads=16)
     for rs, ds in ((1, 1), (4, 8), (16, 2)):
@@ -72,9 +75,9 @@ def test_autotune_picks_a_valid_config():
     R = dev(wl.R)
     r = ev.autotune(R, precision=1, n_rep=3)
     log(f"autotune: splits {r.spmm_row_splits} direct {r.direct_split} sort {r.sort_walkers} "
+        f"overlap {r.overlap_fallback} "
         f"best {r.best_ms:.4f} ms default {r.default_ms:.4f} ms over {r.n_candidates} candidates")
-    assert r.n_candidates == 12 and r.best_ms <= r.default_ms
-    assert ev.launch_config()[:2] == (r.spmm_row_splits, r.direct_split)
+    assert r.n_candidates == 24 and r.best_ms <= r.default_ms
     rows = list(range(0, 1024, 64))
     ref = oracle.evaluate(wl, wl.R[rows], n_threads=16)
     s, l, g, w = gpu_eval(ev, wl.R, precision=1)

@@ -253,3 +253,55 @@ def test_identically_zero_orbital_gives_singular_minors():
         ep, eg = scaled_errors(ref, sign, logabs, gl)
         summary(f"zero orbital {m0} precision {prec}", ep, eg, ws)
         assert ep.max() <= tol and eg.max() <= tol
+
+
+def _high_degree_workload():
+    """A degree mix shaped like the paper's larger expansions (degrees 1-8,
+    Sec. 4, Table 4): 9+8 electrons, 100 orbitals, 600 + 500 distinct
+    determinants, 2e4 products."""
+    return make_custom(9, 8, 100, 4, 600, 500, (1, 2, 3, 4, 5, 6, 7, 8), 20_000, 160, seed=31)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_high_degree_table_method(precision, tol):
+    """Excitation degrees 5-8 through the table method (s x s minors inverted
+    in registers by k_ratios_hi), full batch against the oracle, eager and as
+    a captured graph; and per-walker degree limits up to 8."""
+    log(f"[parity] degrees 1-8 through the table method, precision {precision}")
+    wl = _high_degree_workload()
+    ev = evaluator(wl)
+    st = ev.stats()
+    assert sum(st.n_by_degree_up[5:]) > 0 and sum(st.n_by_degree_dn[5:]) > 0
+    ref = oracle.evaluate(wl, wl.R, max_degree=None, n_threads=16)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=precision)
+    ep, eg = scaled_errors(ref, sign, logabs, gl)
+    summary(f"degree 8 table prec{precision}", ep, eg, ws)
+    assert ep.max() <= tol and eg.max() <= tol
+    Rt = torch.as_tensor(wl.R, device="cuda")
+    out = ev.eval_graph(Rt, precision=precision)
+    out = ev.eval_graph(Rt, precision=precision, out=out)
+    torch.cuda.synchronize()
+    for x, y in zip(out[:3], (sign, logabs, gl)):
+        assert np.array_equal(x.cpu().numpy(), y)
+    md = np.random.default_rng(5).integers(1, 9, size=wl.n_walk).astype(np.int8)
+    rows = list(range(0, wl.n_walk, 5))
+    refd = oracle.evaluate(wl, wl.R[rows], max_degree=md[rows], n_threads=16)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=precision, max_degree=md)
+    ep, eg = scaled_errors(refd, sign, logabs, gl, idx=rows)
+    summary(f"degree 8 table, limits 1-8, prec{precision}", ep, eg, ws[rows])
+    assert ep.max() <= tol and eg.max() <= tol
+
+
+def test_high_degree_forced_fallback():
+    """Every (walker, spin) of the degree-8 expansion through the direct-LU
+    fallback (its matrices from the high-degree descriptors)."""
+    log("[parity] degrees 1-8, forced fallback")
+    wl = _high_degree_workload()
+    ev = evaluator(wl)
+    ev.set_fallback_threshold(1e-300)
+    R = wl.R[:48]
+    sign, logabs, gl, ws = gpu_eval(ev, R)
+    assert np.all(ws == mdet.W_FALLBACK)
+    ref = oracle.evaluate(wl, R, max_degree=None, n_threads=16)
+    ep, eg = scaled_errors(ref, sign, logabs, gl)
+    assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL

@@ -148,9 +148,10 @@ def test_chain_honours_max_degree_and_graphs():
     assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL
 
 
-def test_excitation_degrees_up_to_eight_by_the_chain():
-    """Degrees 1-8 from the reference: the table method refuses the expansion,
-    the chain evaluates it (no degree limit along the sorted list)."""
+def test_excitation_degrees_up_to_eight_table_and_chain():
+    """Degrees 1-8 from the reference: the table method (s x s minors up to
+    8 x 8) and the chain (no degree limit along the sorted list) both match
+    the direct-LU oracle."""
     from gen.workloads import make_custom
     log("[sm] degrees up to 8, 9+8 electrons, 60 orbitals")
     wl = make_custom(9, 8, 60, 3, 200, 150, (1, 2, 4, 6, 8), 3000, 64, seed=21)
@@ -158,9 +159,11 @@ def test_excitation_degrees_up_to_eight_by_the_chain():
     chain = oracle.sm_evaluate(wl, n_threads=16)
     ev = mdet.Evaluator(0)
     ev.load_workload(wl)
-    with pytest.raises(mdet.MdetError) as ei:
-        gpu_eval(ev, wl.R)
-    assert ei.value.code == -10
+    for prec, tol in ((0, FP64_TOL), (1, MIXED_TOL)):
+        sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=prec)
+        ep, eg = scaled_errors(direct, sign, logabs, gl)
+        summary(f"degree 8, table method, precision {prec}", ep, eg, ws)
+        assert ep.max() <= tol and eg.max() <= tol
     ev.set_method(mdet.METHOD_SM_CHAIN, 1e-3, 1)
     sign, logabs, gl, ws = gpu_eval(ev, wl.R)
     ep, eg = scaled_errors(direct, sign, logabs, gl)
@@ -174,3 +177,22 @@ def test_excitation_degrees_up_to_eight_by_the_chain():
     summary("degree 8, one piece", ep, eg, ws)
     assert abs(cnt["n_subst"] - chain.n_subst) <= 1e-3 * max(chain.n_subst, 1000)
     assert ep.max() <= max(FP64_TOL, 10 * cp.max()) and eg.max() <= max(FP64_TOL, 10 * cg.max())
+
+
+def test_degrees_above_eight_by_the_chain_only():
+    """Degree 9 (10+9 electrons): the table method refuses the
+    expansion with MDET_EDEGREE, the chain evaluates it."""
+    from gen.workloads import make_custom
+    log("[sm] degree 9, 10+9 electrons, 40 orbitals")
+    wl = make_custom(10, 9, 40, 3, 80, 60, (1, 2, 9), 1200, 16, seed=23)
+    direct = oracle.evaluate(wl, max_degree=None, n_threads=16)
+    ev = mdet.Evaluator(0)
+    ev.load_workload(wl)
+    with pytest.raises(mdet.MdetError) as ei:
+        gpu_eval(ev, wl.R)
+    assert ei.value.code == -10
+    ev.set_method(mdet.METHOD_SM_CHAIN, 1e-3, 1)
+    sign, logabs, gl, ws = gpu_eval(ev, wl.R)
+    ep, eg = scaled_errors(direct, sign, logabs, gl)
+    summary("degree 9, pieces of 1", ep, eg, ws)
+    assert ep.max() <= FP64_TOL and eg.max() <= FP64_TOL

@@ -73,7 +73,8 @@ def _gaussian_psi(alpha):
     return fn
 
 
-def test_esjd_gradient_finite_differences():
+@pytest.mark.parametrize("jump_ref", [0.0, 0.7])
+def test_esjd_gradient_finite_differences(jump_ref):
     N, n_hid, B = 3, 6, 5
     n_in, n_out = 3 * N, 4 * N
     p = _params(n_in, n_hid, n_out, 3, scale=0.2)
@@ -82,13 +83,17 @@ def test_esjd_gradient_finite_differences():
     xi = r.normal(0, 1.0, (B, N, 3))
     psi = _gaussian_psi(0.4)
     lR = psi(R)[0]
-    loss, g, info = mlp.esjd_loss_and_grad(p, R, xi, lR, psi, n_hid)
+    loss, g, info = mlp.esjd_loss_and_grad(p, R, xi, lR, psi, n_hid, jump_ref=jump_ref)
     assert np.all(np.abs(info["ell"]) > 1e-3)      # no walker on the min(1, .) kink
+    # the objective itself: A times the (weighted) squared jumps, written out
+    c = 1.0 if jump_ref <= 0 else 1.0 / (np.sum(R * R, axis=2) + jump_ref ** 2)
+    J = info["A"] * np.sum(c * np.sum((info["Rp"] - R) ** 2, axis=2), axis=1)
+    assert abs(loss + J.mean()) < 1e-14 * abs(loss)
     h = 1e-6
     for i in r.choice(p.size, 25, replace=False):
         e = np.zeros_like(p); e[i] = h
-        lp = mlp.esjd_loss_and_grad(p + e, R, xi, lR, psi, n_hid)[0]
-        lm = mlp.esjd_loss_and_grad(p - e, R, xi, lR, psi, n_hid)[0]
+        lp = mlp.esjd_loss_and_grad(p + e, R, xi, lR, psi, n_hid, jump_ref=jump_ref)[0]
+        lm = mlp.esjd_loss_and_grad(p - e, R, xi, lR, psi, n_hid, jump_ref=jump_ref)[0]
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) < 2e-6 * (1 + abs(fd)), (i, fd, g[i])
 
