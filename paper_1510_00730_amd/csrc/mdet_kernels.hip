@@ -607,53 +607,82 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
 
 namespace {
 
-// T = X Phi' of one (walker, spin) into LDS: T[c][m] = sum_e X[c][e] phi[e][m] 2^-E[m]
-// (X in LDS, row-major n x n; phis = values of the spin's first electron, row
-// stride 5 M).  One column m per thread, e ascending.  The values of column
-// m = tid come in `col0`, loaded by pair_setup before the set-up barrier.
-__device__ __forceinline__ void table_column_load(const double *phis, int n, int M, int m,
-                                                  double col[kMaxN]) {
-#pragma unroll
-    for (int e = 0; e < kMaxN; ++e) col[e] = (e < n && m < M) ? phis[(size_t)e * 5 * M + m] : 0.0;
+// Dense FP64 contractions of one (walker, spin) on the matrix cores:
+// v_mfma_f64_16x16x4_f64 adds a 16 x 4 block A times a 4 x 16 block B to a
+// 16 x 16 block D; lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] of a
+// step and D[l / 16 + 4 i][l % 16] in accumulator i = 0..3 (the FP64 form
+// interleaves the rows, unlike the FP32 one).  Every lane of the wave takes
+// part (out-of-range entries are zero).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma_f64(double a, double b, v4d c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ void table_column(int n, int M, int m, const int *Ex, const double *X,
-                                             double col[kMaxN], double *T) {
-    const double s = pow2(-Ex[m]);
+constexpr int kKSteps = kMaxN / 4;  // steps of 4 over an electron or slot index
+
+// The orbital values of one table tile of 16 orbitals m0.. as the B operand:
+// b[s] = phi[4s + l/16][m0 + l%16] (unscaled; phis has row stride 5 M).
+__device__ __forceinline__ void table_tile_load(const double *phis, int n, int M, int m0, int lane,
+                                                double (&b)[kKSteps]) {
+    const int li = lane & 15, lk = lane >> 4, m = m0 + li;
 #pragma unroll
-    for (int e = 0; e < kMaxN; ++e) col[e] *= s;
-    for (int c = 0; c < n; ++c) {
-        double t = 0.0;
-#pragma unroll
-        for (int e = 0; e < kMaxN; ++e)
-            if (e < n) t += X[c * n + e] * col[e];
-        T[c * M + m] = t;
+    for (int s = 0; s < kKSteps; ++s) {
+        const int e = 4 * s + lk;
+        b[s] = (e < n && m < M) ? phis[(size_t)e * 5 * M + m] : 0.0;
     }
 }
 
+// T = X Phi' of one (walker, spin) into LDS: T[c][m] = sum_e X[c][e] phi[e][m]
+// 2^-E[m] (X in LDS, row-major n x n), on the matrix cores: the waves of the
+// block take tiles of 16 orbitals in turn, K = n in steps of 4.  The values
+// of the wave's first tile come in b0 (loaded before the set-up barrier).
 __device__ __forceinline__ void build_table(const double *phis, int n, int M, const int *Ex,
                                             const double *X, double *T, int tid, int nthr,
-                                            double col0[kMaxN]) {
-    if (tid < M) table_column(n, M, tid, Ex, X, col0, T);
-    for (int m = tid + nthr; m < M; m += nthr) {
-        double col[kMaxN];
-        table_column_load(phis, n, M, m, col);
-        table_column(n, M, m, Ex, X, col, T);
+                                            double (&b0)[kKSteps]) {
+    const int lane = tid & 63, wave = tid >> 6, nwave = nthr >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int ksteps = (n + 3) >> 2;
+    double xa[kKSteps];
+#pragma unroll
+    for (int s = 0; s < kKSteps; ++s) {
+        const int e = 4 * s + lk;
+        xa[s] = (li < n && e < n) ? X[li * n + e] : 0.0;
+    }
+    for (int m0 = 16 * wave; m0 < M; m0 += 16 * nwave) {
+        double b[kKSteps];
+        if (m0 == 16 * wave) {
+#pragma unroll
+            for (int s = 0; s < kKSteps; ++s) b[s] = b0[s];
+        } else {
+            table_tile_load(phis, n, M, m0, lane, b);
+        }
+        const int m = m0 + li;
+        const double sc = m < M ? pow2(-Ex[m]) : 0.0;
+        v4d d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < kKSteps; ++s)
+            if (s < ksteps) d = mfma_f64(xa[s], b[s] * sc, d);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int c = lk + 4 * i;
+            if (c < n && m < M) T[c * M + m] = d[i];
+        }
     }
 }
 
 // Set-up of the kernels that rebuild T for one (walker, spin): X, the column
 // exponents and the reference occupation into LDS, and the orbital values of
-// the thread's first table column into col0, every load issued before the
-// first is waited for (one round trip to memory, not one per array).
+// the wave's first table tile into b0, every load issued before the first is
+// waited for (one round trip to memory, not one per array).
 static_assert(kMaxN * kMaxN <= kBlock, "one X entry per thread");
 __device__ __forceinline__ void pair_setup(const double *Xg, const int *Eg, const int *occg,
                                            const double *phis, int n, int M, int tid, double *X,
-                                           int *Ex, int *occ0, double col0[kMaxN]) {
+                                           int *Ex, int *occ0, double (&b0)[kKSteps]) {
     const double xv = tid < n * n ? Xg[tid] : 0.0;
     const int ev = tid < M ? Eg[tid] : 0;
     const int ov = tid < n ? occg[tid] : 0;
-    table_column_load(phis, n, M, tid, col0);
+    table_tile_load(phis, n, M, 16 * (tid >> 6), tid & 63, b0);
     if (tid < n * n) X[tid] = xv;
     if (tid < M) Ex[tid] = ev;
     if (tid < n) occ0[tid] = ov;
@@ -756,7 +785,7 @@ __global__ void __launch_bounds__(kBlock, 1) k_ratios_hi(KernelArgs a) {
     int *occ0 = Ex + M;              // [n]
     __shared__ int red[kBlock];
     const double *phis = a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M;
-    double col0[kMaxN];
+    double col0[kKSteps];
     pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
                occ0, col0);
     __syncthreads();
@@ -808,7 +837,7 @@ __global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
     int *occ0 = Ex + M;              // [n]
     __shared__ int red[kBlock];
     const double *phis = a.wk.phi + ((size_t)w * a.N + S.e0) * 5 * M;
-    double col0[kMaxN];
+    double col0[kKSteps];
     pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
                occ0, col0);
     __syncthreads();
@@ -1079,7 +1108,8 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
 // first by the chunk loop (adjugates cb [kAdjChunk], gather pointers
 // [n*M + 1], gather positions [kAdjChunk]) and afterwards by Y [M][n],
 // Zc [n][n] and kDerivScratch partial sums; then Ex [M] and occ0 [n].
-constexpr int kDerivScratch = 256;
+constexpr int kDerivScratch = 4 * 256;  // the waves' 16 x 16 partial blocks of Zc
+static_assert(kDerivScratch >= (kBlock / 64) * 256, "Zc partials");
 constexpr int kGpReg = 4;                   // gather pointers per thread held in registers
 constexpr int kGqReg = kAdjChunk / 256;     // gather positions per thread (all of them)
 
@@ -1110,7 +1140,7 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
     int *Ex = (int *)(un + deriv_union_doubles(n, M));  // [M]
     int *occ0 = Ex + M;               // [n]
     const double *phis = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
-    double col0[kMaxN];
+    double col0[kKSteps];
     pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
                occ0, col0);
     for (int i = tid; i < nt; i += kBlock) Gam[i] = 0.0;
@@ -1213,32 +1243,61 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
         }
         __syncthreads();
     }
-    for (int idx = tid; idx < M * n; idx += kBlock) {
-        const int m = idx / n, e = idx - m * n;
-        double s = 0.0;
-        for (int c = 0; c < n; ++c) s += Gam[c * M + m] * X[c * n + e];
-        Y[idx] = s;
+    // Y = Gamma^T X on the matrix cores (Y[m][e], row stride n): tiles of 16
+    // orbitals m, K = the n slots c in steps of 4
+    {
+        const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+        const int ksteps = (n + 3) >> 2;
+        double xb[kKSteps];
+#pragma unroll
+        for (int s = 0; s < kKSteps; ++s) {
+            const int c = 4 * s + lk;
+            xb[s] = (c < n && li < n) ? X[c * n + li] : 0.0;
+        }
+        for (int m0 = 16 * wave; m0 < M; m0 += 16 * (kBlock / 64)) {
+            const int m = m0 + li;
+            v4d d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < kKSteps; ++s) {
+                const int c = 4 * s + lk;
+                const double ga = (c < n && m < M) ? Gam[c * M + m] : 0.0;
+                if (s < ksteps) d = mfma_f64(ga, xb[s], d);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int mm = m0 + lk + 4 * i;
+                if (mm < M && li < n) Y[mm * n + li] = d[i];
+            }
+        }
     }
     __syncthreads();
-    // Zc = T Y: nz segments of m per entry, partial sums in scr
-    const int nz = max(1, min(4, kDerivScratch / (n * n)));
-    if (tid < nz * n * n) {
-        const int idx = tid / nz, g = tid - idx * nz;
-        const int c = idx / n, e = idx - c * n;
-        double s = 0.0;
-        for (int m = g; m < M; m += nz) s += T[c * M + m] * Y[m * n + e];
-        scr[tid] = s;
+    // Zc = T Y on the matrix cores: one 16 x 16 block (c, e), K = the M
+    // orbitals in steps of 4 dealt to the waves in turn; the waves' partial
+    // blocks are added in wave order
+    {
+        const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
+        v4d d = {0.0, 0.0, 0.0, 0.0};
+        for (int m0 = 4 * wave; m0 < M; m0 += 4 * (kBlock / 64)) {
+            const int m = m0 + lk;
+            const double ta = (li < n && m < M) ? T[li * M + m] : 0.0;
+            const double yb = (m < M && li < n) ? Y[m * n + li] : 0.0;
+            d = mfma_f64(ta, yb, d);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) scr[wave * 256 + (lk + 4 * i) * 16 + li] = d[i];
     }
     __syncthreads();
     for (int idx = tid; idx < n * n; idx += kBlock) {
+        const int c = idx / n, e = idx - c * n;
         double s = 0.0;
-        for (int g = 0; g < nz; ++g) s += scr[idx * nz + g];
+#pragma unroll
+        for (int g = 0; g < kBlock / 64; ++g) s += scr[g * 256 + c * 16 + e];
         Zc[idx] = s;
     }
     __syncthreads();
     // s1[e][q] = sum_m G_q[e][m] 2^-E[m] Y[m][e]: nf segments of m per (e, q),
     // eight loads in flight per step
-    const int nf = max(1, min(8, kDerivScratch / (4 * n)));
+    const int nf = max(1, min(8, 256 / (4 * n)));
     const double *phig = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
     if (tid < nf * 4 * n) {
         const int pr = tid / nf, g = tid - pr * nf;
@@ -1838,10 +1897,10 @@ __global__ void __launch_bounds__(256) k_sort_scatter(int64_t W, int N, const in
 namespace {
 
 template <int NT>
-void launch_direct(const KernelArgs &a, hipStream_t st, bool deriv) {
+void launch_direct(const KernelArgs &a, hipStream_t st, bool deriv, int cap) {
     const int M = a.M;
     // a fixed grid walks the (pair, part) items; at most 2 W of them per part
-    const unsigned grid = (unsigned)std::min<int64_t>(2 * a.W * a.direct_split, 1024);
+    const unsigned grid = (unsigned)std::min<int64_t>(2 * a.W * a.direct_split, cap);
     if (deriv) {
         const size_t lds = sizeof(double) * ((a.direct_stage_grad ? 5 : 1) * (size_t)NT * M +
                                              (kDirectBlock / 64) * (NT * 4 + 64 * kWredLd)) +
@@ -1853,24 +1912,26 @@ void launch_direct(const KernelArgs &a, hipStream_t st, bool deriv) {
     }
 }
 
-void launch_direct_n(const KernelArgs &a, hipStream_t st, bool deriv) {
+// cap: most blocks of the fixed grid (each block is placed on a CU before it
+// finds no item left, so a grid beside another kernel is kept small)
+void launch_direct_n(const KernelArgs &a, hipStream_t st, bool deriv, int cap = 1024) {
     switch (a.nmax) {  // the larger electron count (n_up)
-    case 1: launch_direct<1>(a, st, deriv); break;
-    case 2: launch_direct<2>(a, st, deriv); break;
-    case 3: launch_direct<3>(a, st, deriv); break;
-    case 4: launch_direct<4>(a, st, deriv); break;
-    case 5: launch_direct<5>(a, st, deriv); break;
-    case 6: launch_direct<6>(a, st, deriv); break;
-    case 7: launch_direct<7>(a, st, deriv); break;
-    case 8: launch_direct<8>(a, st, deriv); break;
-    case 9: launch_direct<9>(a, st, deriv); break;
-    case 10: launch_direct<10>(a, st, deriv); break;
-    case 11: launch_direct<11>(a, st, deriv); break;
-    case 12: launch_direct<12>(a, st, deriv); break;
-    case 13: launch_direct<13>(a, st, deriv); break;
-    case 14: launch_direct<14>(a, st, deriv); break;
-    case 15: launch_direct<15>(a, st, deriv); break;
-    default: launch_direct<16>(a, st, deriv); break;  // nmax <= MDET_MAX_SPIN_ELEC = 16
+    case 1: launch_direct<1>(a, st, deriv, cap); break;
+    case 2: launch_direct<2>(a, st, deriv, cap); break;
+    case 3: launch_direct<3>(a, st, deriv, cap); break;
+    case 4: launch_direct<4>(a, st, deriv, cap); break;
+    case 5: launch_direct<5>(a, st, deriv, cap); break;
+    case 6: launch_direct<6>(a, st, deriv, cap); break;
+    case 7: launch_direct<7>(a, st, deriv, cap); break;
+    case 8: launch_direct<8>(a, st, deriv, cap); break;
+    case 9: launch_direct<9>(a, st, deriv, cap); break;
+    case 10: launch_direct<10>(a, st, deriv, cap); break;
+    case 11: launch_direct<11>(a, st, deriv, cap); break;
+    case 12: launch_direct<12>(a, st, deriv, cap); break;
+    case 13: launch_direct<13>(a, st, deriv, cap); break;
+    case 14: launch_direct<14>(a, st, deriv, cap); break;
+    case 15: launch_direct<15>(a, st, deriv, cap); break;
+    default: launch_direct<16>(a, st, deriv, cap); break;  // nmax <= MDET_MAX_SPIN_ELEC = 16
     }
 }
 
@@ -1955,11 +2016,14 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev, cons
     k_reference<<<dim3(W), blk, lds_ref, st>>>(a);
     mark(0, true, st);
     if (a.method == MDET_METHOD_SM_CHAIN) return launch_chain(a, st, ev);
-    const unsigned gscale = (unsigned)std::min<int64_t>(2 * (int64_t)W * a.direct_split, 1024);
+    // beside the table-method kernels the fallback's grids are kept small: it
+    // has their whole duration, and every block of a grid takes a CU slot
+    const int cap_r = ovl ? 256 : 1024, cap_d = ovl ? 128 : 1024;
+    const unsigned gscale = (unsigned)std::min<int64_t>(2 * (int64_t)W * a.direct_split, cap_r);
     auto fallback_ratios = [&]() {
         mark(2, false, sf);
         k_direct_list<<<dim3(1), dim3(1024), 0, sf>>>(a);
-        launch_direct_n(a, sf, false);
+        launch_direct_n(a, sf, false, cap_r);
         k_direct_scale<<<dim3(gscale), blk, 0, sf>>>(a);
         mark(2, true, sf);
     };
@@ -1993,7 +2057,7 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev, cons
     if (ovl) {
         fork(aux->ev[2], st, sf);
         mark(5, false, sf);
-        launch_direct_n(a, sf, true);
+        launch_direct_n(a, sf, true, cap_d);
         mark(5, true, sf);
         if (err == hipSuccess) err = hipEventRecord(aux->ev[3], sf);
     }
