@@ -464,7 +464,7 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
  * joined before the kernels that read them; also inside captured graphs).
  * FP64 results are bitwise reproducible for a fixed configuration (the
  * summation grouping depends on the splits; the overlap does not change
- * results).  Default (0, 0, 1, 1).  Setting it drops captured graphs and the
+ * results).  Default (0, 0, 1, 0).  Setting it drops captured graphs and the
  * configurations mdet_autotune remembered.
  */
 mdet_status mdet_set_launch_config(mdet_ctx *ctx, int32_t spmm_row_splits, int32_t direct_split,
@@ -493,7 +493,7 @@ typedef struct {
 
 /*
  * Time every candidate launch configuration (row splits {auto, 4, 8, 16} x
- * fallback splits {auto, 2, 4} x fallback overlap {on, off} x walker sorting
+ * fallback splits {auto, 4, 8} x fallback overlap {on, off} x walker sorting
  * {on, off} when max_degree_dev is given) on n_rep evaluations of the given
  * walkers and report the fastest in *out (nullable).  The context remembers
  * it for this shape -- (n_walk, precision, with or without per-walker degree

@@ -375,7 +375,7 @@ class Evaluator:
 
     # -------------------------------------------------------------- tuning / graphs
     def set_launch_config(self, spmm_row_splits=0, direct_split=0, sort_walkers=True,
-                          overlap_fallback=True):
+                          overlap_fallback=False):
         self._check(_LIB.mdet_set_launch_config(self._h, int(spmm_row_splits), int(direct_split),
                                                 1 if sort_walkers else 0,
                                                 1 if overlap_fallback else 0))

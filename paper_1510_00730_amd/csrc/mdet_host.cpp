@@ -118,7 +118,7 @@ struct mdet_ctx {
     DevBuf d_rptr, d_rcol, d_rval, d_rseg, d_cptr, d_crow, d_cval, d_cseg;
     DevBuf d_rseg32, d_cseg32, d_rdeg, d_cdeg;
     int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
-    LaunchCfg cfg{0, 0, 1, 1};
+    LaunchCfg cfg{0, 0, 1, 0};
     // configurations found by mdet_autotune, per shape
     struct TunedShape {
         int64_t W;
@@ -1741,7 +1741,7 @@ mdet_status mdet_autotune(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, in
             HIP_OK(hipEventCreate(&e1));
             std::vector<LaunchCfg> cand;
             for (int rs : {0, 4, 8, 16})
-                for (int ds : {0, 2, 4})
+                for (int ds : {0, 4, 8})
                     for (int ov : {1, 0})
                         for (int so : {1, 0}) {
                             if (!max_degree_dev && so == 0) continue;
