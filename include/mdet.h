@@ -427,24 +427,28 @@ mdet_status mdet_mlp_adam(mdet_ctx *ctx, int64_t n, float *params, const float *
 
 /*
  * One training step of the proposal network on walker samples R_dev
- * [W][N][3] with move noise noise_dev [W][N][3]: maximises the expected
- * (weighted) squared jump distance with the exact acceptance,
- *   loss = -mean_w A_w sum_e c_e |r'_e - r_e|^2,  R' = R + mu(R) + sigma(R) xi,
+ * [W][N][3] with move noise noise_dev [W][N][3]: maximises the expected jump
+ * of a statistic with the exact acceptance,
+ *   loss = -mean_w A_w jump_w,  R' = R + mu(R) + sigma(R) xi,
  *   A = min(1, |Psi(R')/Psi(R)|^2 q(R|R')/q(R'|R)),
- * with c_e = 1 when jump_ref <= 0 (the plain jump distance) and
- * c_e = 1 / (|r_e|^2 + jump_ref^2) otherwise (each electron's jump relative to
- * its distance from the nucleus, so that moves of the inner electrons, which
- * dominate the local energy, weigh as much as those of the outer ones),
+ * with, for objective MDET_OBJ_JUMP, jump = sum_e c_e |r'_e - r_e|^2 (c_e = 1
+ * when jump_ref <= 0, the plain squared jump distance; c_e = 1 / (|r_e|^2 +
+ * jump_ref^2) otherwise, each electron's jump relative to its distance from
+ * the nucleus), and for MDET_OBJ_POTENTIAL, jump = (V(R') - V(R))^2 with V the
+ * Coulomb potential energy of the electrons around a point nucleus of charge
+ * nuclear_charge at the origin (the part of the local energy a move changes
+ * most, so decorrelating V targets the local energy's autocorrelation);
  * differentiating through both network evaluations, through ln|Psi(R')|
  * (grad ln|Psi| from the multideterminant path) and through q; then one Adam
  * step (beta 0.9/0.999, eps 1e-8).  loss_dev: double [1]; grad_dev: float
  * [n_params] or null (gradient before the update).
  */
+enum { MDET_OBJ_JUMP = 0, MDET_OBJ_POTENTIAL = 1 };
 mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden, float *params,
                                 float *adam_m, float *adam_v, int32_t t, float lr,
                                 const double *R_dev, const double *noise_dev, int32_t precision,
-                                double jump_ref, double *loss_dev, float *grad_dev,
-                                void *hip_stream);
+                                double jump_ref, int32_t objective, double nuclear_charge,
+                                double *loss_dev, float *grad_dev, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Launch configuration, captured steps and tuning.

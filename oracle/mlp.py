@@ -94,9 +94,29 @@ def log_q(Rb, Ra, mu_a, ls_a):
     return np.sum(-np.sum(d * d, axis=2) / (2.0 * np.exp(2.0 * ls_a)) - 3.0 * ls_a, axis=1)
 
 
-def esjd_loss_and_grad(flat, R, xi, logpsi_R, psi_fn, n_hid, jump_ref=0.0):
-    """Loss -mean(A sum_e c_e |r'_e - r_e|^2) and its exact gradient w.r.t.
-    the parameters; c_e = 1, or 1 / (|r_e|^2 + jump_ref^2) when jump_ref > 0.
+def coulomb_potential(R, Z):
+    """V = -Z sum_e 1/|r_e| + sum_{e<f} 1/|r_e - r_f| per walker and its
+    gradient [B][N][3] (nucleus of charge Z at the origin)."""
+    r = np.linalg.norm(R, axis=2)
+    V = -Z * np.sum(1.0 / r, axis=1)
+    g = Z * R / r[:, :, None] ** 3
+    N = R.shape[1]
+    for e in range(N):
+        for f in range(e + 1, N):
+            d = R[:, e] - R[:, f]
+            dn = np.linalg.norm(d, axis=1)
+            V += 1.0 / dn
+            c = (d / dn[:, None] ** 3)
+            g[:, e] -= c
+            g[:, f] += c
+    return V, g
+
+
+def esjd_loss_and_grad(flat, R, xi, logpsi_R, psi_fn, n_hid, jump_ref=0.0, objective=0, Z=0.0):
+    """Loss -mean(A jump) and its exact gradient w.r.t. the parameters:
+    objective 0, jump = sum_e c_e |r'_e - r_e|^2 with c_e = 1, or
+    1 / (|r_e|^2 + jump_ref^2) when jump_ref > 0; objective 1,
+    jump = (V(R') - V(R))^2 with V the Coulomb potential (nuclear charge Z).
 
     R [B][N][3], xi [B][N][3]; logpsi_R [B] = ln|Psi(R)|; psi_fn(R') returns
     (ln|Psi(R')| [B], grad ln|Psi(R')| [B][N][3]).  Returns (loss, grad, info).
@@ -117,14 +137,21 @@ def esjd_loss_and_grad(flat, R, xi, logpsi_R, psi_fn, n_hid, jump_ref=0.0):
     lq_rev = np.sum(-np.sum(d * d, axis=2) / (2.0 * np.exp(2.0 * ls2)) - 3.0 * ls2, axis=1)
     ell = 2.0 * (lp - logpsi_R) + lq_rev - lq_fwd
     A = np.minimum(1.0, np.exp(np.minimum(ell, 0.0)))
-    cw = np.ones((B, N)) if jump_ref <= 0 else 1.0 / (np.sum(R * R, axis=2) + jump_ref ** 2)
-    jump = np.sum(cw * np.sum((Rp - R) ** 2, axis=2), axis=1)
+    if objective == 1:
+        Vp, dVp = coulomb_potential(Rp, Z)
+        dv = Vp - coulomb_potential(R, Z)[0]
+        jump = dv * dv
+        djump = 2.0 * dv[:, None, None] * dVp
+    else:
+        cw = np.ones((B, N)) if jump_ref <= 0 else 1.0 / (np.sum(R * R, axis=2) + jump_ref ** 2)
+        jump = np.sum(cw * np.sum((Rp - R) ** 2, axis=2), axis=1)
+        djump = 2.0 * cw[:, :, None] * (Rp - R)
     J = A * jump
     loss = -np.mean(J)
     # d loss / d J_w = -1/B
     gJ = -np.ones(B) / B
     g_ell = gJ * np.where(ell < 0.0, A, 0.0) * jump
-    g_Rp = gJ[:, None, None] * A[:, None, None] * 2.0 * cw[:, :, None] * (Rp - R)
+    g_Rp = gJ[:, None, None] * A[:, None, None] * djump
     # ell: 2 lnPsi(R') + lq_rev(R', mu2, ls2) - lq_fwd(ls)
     g_Rp += g_ell[:, None, None] * (2.0 * glp + d / s2)
     g_mu2 = g_ell[:, None, None] * (d / s2)

@@ -36,6 +36,7 @@ EXPORTED = ["mdet_create", "mdet_destroy", "mdet_last_error", "mdet_init_orbital
             "mdet_set_profiling_mask", "mdet_eval_walkers_noalloc"]
 METHOD_TABLE, METHOD_SM_CHAIN = 0, 1
 PROP_GAUSSIAN, PROP_DRIFT, PROP_MLP = 0, 1, 2
+OBJ_JUMP, OBJ_POTENTIAL = 0, 1
 RNG_UNIFORM, RNG_NORMAL = 0, 1
 
 
@@ -96,8 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mdet_mlp_backward": (I32, [P, I32, I32, I32, P, I64, P, P, P, P, P]),
         "mdet_mlp_adam": (I32, [P, I64, P, P, P, P, I32, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float, P]),
-        "mdet_mlp_train_step": (I32, [P, I64, I32, P, P, P, I32, ctypes.c_float, P, P, I32, D, P, P,
-                                      P]),
+        "mdet_mlp_train_step": (I32, [P, I64, I32, P, P, P, I32, ctypes.c_float, P, P, I32, D, I32,
+                                      D, P, P, P]),
         "mdet_set_launch_config": (I32, [P, I32, I32, I32, I32]),
         "mdet_get_launch_config": (I32, [P, P, P, P, P]),
         "mdet_eval_graph": (I32, [P, I64, P, I32, P, P, P, P, P, P]),
@@ -365,13 +366,18 @@ class Evaluator:
                                        self._stream(stream)))
 
     def mlp_train_step(self, params, m, v, t, lr, R, noise, n_hidden, loss, grad=None,
-                       precision=MDET_FP64, jump_ref=0.0, stream=None):
+                       precision=MDET_FP64, jump_ref=0.0, objective=OBJ_JUMP,
+                       nuclear_charge=None, stream=None):
         """One training step (see mdet_mlp_train_step); jump_ref > 0 weighs each
-        electron's squared jump by 1 / (|r_e|^2 + jump_ref^2)."""
+        electron's squared jump by 1 / (|r_e|^2 + jump_ref^2); objective
+        OBJ_POTENTIAL maximises the expected squared change of the Coulomb
+        potential energy (nucleus of charge nuclear_charge, default N)."""
+        Z = float(self.n_up + self.n_dn) if nuclear_charge is None else float(nuclear_charge)
         self._check(_LIB.mdet_mlp_train_step(self._h, R.shape[0], int(n_hidden), _dptr(params),
                                              _dptr(m), _dptr(v), int(t), float(lr), _dptr(R),
                                              _dptr(noise), int(precision), float(jump_ref),
-                                             _dptr(loss), _dptr(grad), self._stream(stream)))
+                                             int(objective), Z, _dptr(loss), _dptr(grad),
+                                             self._stream(stream)))
 
     # -------------------------------------------------------------- tuning / graphs
     def set_launch_config(self, spmm_row_splits=0, direct_split=0, sort_walkers=True,

@@ -115,7 +115,7 @@ struct mdet_ctx {
     std::vector<int32_t> row_i, col_j;
     std::vector<double> val;
     std::vector<int64_t> src_pos;
-    DevBuf d_rptr, d_rcol, d_rval, d_rseg, d_cptr, d_crow, d_cval, d_cseg;
+    DevBuf d_rptr, d_rcol, d_rval, d_rseg, d_cptr, d_crow, d_cval, d_cseg, d_rval32, d_cval32;
     DevBuf d_rseg32, d_cseg32, d_rdeg, d_cdeg;
     int32_t nch_r = 1, nch_c = 1, nch_r32 = 1, nch_c32 = 1;
     LaunchCfg cfg{0, 0, 1, 0};
@@ -248,7 +248,8 @@ struct mdet_ctx {
             s = SpinHost();
         }
         drop_vmc();
-        for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rseg, &d_cptr, &d_crow, &d_cval,
+        for (DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rseg, &d_cptr, &d_crow, &d_cval, &d_rval32,
+                          &d_cval32,
                           &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             b->release();
         drop_work();
@@ -274,7 +275,8 @@ struct mdet_ctx {
     }
     int64_t exp_bytes() const {
         int64_t t = (int64_t)(d_prim.bytes + d_prim_dn.bytes);
-        for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rseg, &d_cptr, &d_crow,
+        for (const DevBuf *b : {&d_rptr, &d_rcol, &d_rval, &d_rseg, &d_cptr, &d_crow, &d_rval32,
+                                &d_cval32,
                                 &d_cval, &d_cseg, &d_rseg32, &d_cseg32, &d_rdeg, &d_cdeg})
             t += (int64_t)b->bytes;
         for (const auto &s : sp)
@@ -790,6 +792,8 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
     a.C.cptr = ctx->d_cptr.as<int32_t>();
     a.C.crow = ctx->d_crow.as<int32_t>();
     a.C.cval = ctx->d_cval.as<double>();
+    a.C.rval32 = ctx->d_rval32.as<float>();
+    a.C.cval32 = ctx->d_cval32.as<float>();
     a.C.rseg64 = ctx->d_rseg.as<int32_t>();
     a.C.cseg64 = ctx->d_cseg.as<int32_t>();
     a.C.rseg32 = ctx->d_rseg32.as<int32_t>();
@@ -1107,6 +1111,8 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->d_cptr.upload(cptr);
             ctx->d_crow.upload(crow);
             ctx->d_cval.upload(cval);
+            ctx->d_rval32.upload(std::vector<float>(rval.begin(), rval.end()));
+            ctx->d_cval32.upload(std::vector<float>(cval.begin(), cval.end()));
             ctx->d_rseg.upload(rseg);
             ctx->d_cseg.upload(cseg);
             ctx->d_rseg32.upload(rseg32);
@@ -1564,10 +1570,13 @@ mdet_status mdet_mlp_adam(mdet_ctx *ctx, int64_t n, float *params, const float *
 mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden, float *params,
                                 float *adam_m, float *adam_v, int32_t t, float lr,
                                 const double *R_dev, const double *noise_dev, int32_t precision,
-                                double jump_ref, double *loss_dev, float *grad_dev,
-                                void *hip_stream) {
+                                double jump_ref, int32_t objective, double nuclear_charge,
+                                double *loss_dev, float *grad_dev, void *hip_stream) {
     return guarded(ctx, [&] {
         require(std::isfinite(jump_ref), MDET_EINVAL, "jump_ref must be finite");
+        require(objective == MDET_OBJ_JUMP || objective == MDET_OBJ_POTENTIAL, MDET_EINVAL,
+                "unknown training objective");
+        require(std::isfinite(nuclear_charge), MDET_EINVAL, "nuclear charge must be finite");
         require(!ctx->host_only, MDET_ESTATE, "host-only context");
         require(ctx->have_exp, MDET_ESTATE, "mdet_set_expansion must come first");
         require(n_walk >= 1 && n_walk <= (int64_t)1 << 24 && n_hidden >= 1 && n_hidden <= 4096,
@@ -1600,7 +1609,7 @@ mdet_status mdet_mlp_train_step(mdet_ctx *ctx, int64_t n_walk, int32_t n_hidden,
                          ctx->v_signp.as<double>(), ctx->v_logabsp.as<double>(),
                          ctx->v_glp.as<double>(), ctx->m_O1.as<float>(), ctx->m_O2.as<float>(),
                          ctx->m_dO2.as<float>(), ctx->m_gRp.as<double>(), ctx->m_gell.as<double>(),
-                         ctx->m_Jw.as<double>(), jump_ref, st);
+                         ctx->m_Jw.as<double>(), jump_ref, objective, nuclear_charge, st);
         launch_mlp_backward(sh, params, n_walk, ctx->m_Xp.as<float>(), ctx->m_h1b.as<float>(),
                             ctx->m_h2b.as<float>(), ctx->m_dO2.as<float>(), grad, 0,
                             ctx->m_dX2.as<float>(), ctx->m_wh1.as<float>(), ctx->m_wh2.as<float>(), st);

@@ -100,6 +100,7 @@ struct SparseDev {
     const int32_t *cptr;   // [V+1] CSC (columns = down determinants)
     const int32_t *crow;   // [Z]
     const double *cval;    // [Z]
+    const float *rval32, *cval32;  // the coefficients rounded to FP32 (mixed precision)
     const int32_t *cseg64, *cseg32;  // [(nch+1)*V]
     // end of the entries of row i (column j) whose column (row) determinant
     // has degree <= d: rdeg[i*(MDET_MAX_DEGREE+1) + d]
@@ -257,7 +258,8 @@ void launch_mlp_propose(int64_t W, int N, const double *R, const float *o, const
 void launch_esjd_head(int64_t W, int N, const double *R, const double *Rp, const double *xi,
                       const double *logabsR, const double *signp, const double *logabsp,
                       const double *glp, const float *o1, const float *o2, float *dO2,
-                      double *gRp, double *gell, double *Jw, double jump_ref, hipStream_t st);
+                      double *gRp, double *gell, double *Jw, double jump_ref, int objective,
+                      double Z, hipStream_t st);
 void launch_esjd_chain(int64_t W, int N, const double *xi, const float *o1, const double *gRp,
                        const float *dX2, const double *gell, float *dO1, hipStream_t st);
 void launch_esjd_loss(int64_t W, const double *Jw, double *out, hipStream_t st);

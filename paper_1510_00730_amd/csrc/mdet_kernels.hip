@@ -918,14 +918,15 @@ __global__ void __launch_bounds__(kBlock, 8) k_ratios(KernelArgs a) {
 // K5: the two sparse products of Sec. 2.4 for a tile of 64 walkers (one per
 // lane), 16 waves per block:
 //   pass 0:  u = C R_dn  (CSR rows, gathering R_dn)  and the psi partials R_up . u
-//   pass 1:  v = C^T R_up (CSC columns, gathering R_up)
-// A wave owns whole rows, so the entries of C are wave-uniform (scalar loads)
-// and each one feeds 64 multiply-adds; the gathered vector of the 64 walkers
-// sits in LDS, CC entries at a time.  F is the storage type of R, u and v
-// (float in mixed precision: half the bytes and twice the columns per LDS
-// chunk); C and the accumulation are FP64 in both precisions (a product of a
-// float and a double converted from float is exact in FP64).
-// grid.x = walker tiles x row splits, grid.y = pass.
+//   pass 1:  v = C^T R_up (CSC columns, gathering R_up) and the psi partials R_dn . v
+// A wave owns whole rows, so the entries of C are wave-uniform and each one
+// feeds 64 multiply-adds; the gathered vector of the 64 walkers sits in LDS,
+// CC entries at a time.  F is the storage type of R, u and v and A the type
+// of C and of the accumulation: FP64 in FP64 mode; in mixed precision float
+// for both (half the bytes, twice the columns per LDS chunk, FP32 multiply-
+// adds; the psi partials stay FP64 with the FP64 ratios, and the derivative
+// aggregate uses the same stored u and v, so their rounding enters Psi and
+// its derivatives alike).  grid.x = walker tiles x row splits, grid.y = pass.
 // ---------------------------------------------------------------------------
 constexpr int kSpmmWaves = 16;
 constexpr int kSpmmLd = kSpmmTile + 1;  // LDS row pitch of the staged vector
@@ -948,18 +949,18 @@ __device__ __forceinline__ void spmm_block_map(int b, int rsplit, int &tile, int
     rs = y - (y / rsplit) * rsplit;
 }
 
-template <typename F, int CC>
+template <typename F, int CC, typename A>
 __global__ void __launch_bounds__(64 * kSpmmWaves)
     k_spmm(KernelArgs a, const F *__restrict__ R, const double *__restrict__ R64,
            F *__restrict__ uv,
-           const double *__restrict__ rval, const double *__restrict__ cval,
+           const A *__restrict__ rval, const A *__restrict__ cval,
            const int32_t *__restrict__ rcol, const int32_t *__restrict__ crow,
            const int32_t *__restrict__ rseg, const int32_t *__restrict__ cseg, int nch_r, int nch_c,
            int rsplit) {
     __shared__ F G[CC * kSpmmLd];
     __shared__ double red[kSpmmWaves][kSpmmTile];
     __shared__ int Cj[kSpmmWaves][64];     // per wave: LDS offsets of a row's next 64 nonzeros
-    __shared__ double Cv[kSpmmWaves][64];  // and their values
+    __shared__ A Cv[kSpmmWaves][64];       // and their values
     const int pass = blockIdx.y;
     int tile, rs;
     spmm_block_map(blockIdx.x, rsplit, tile, rs);
@@ -973,7 +974,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
     const int nch = pass ? nch_c : nch_r;
     const int32_t *__restrict__ idx = pass ? crow : rcol;
     const int32_t *__restrict__ seg = pass ? cseg : rseg;
-    const double *__restrict__ val = pass ? cval : rval;
+    const A *__restrict__ val = pass ? cval : rval;
     const size_t RV = (size_t)a.wk.Upad + a.wk.Vpad;
     const size_t goff = pass ? 0 : (size_t)a.wk.Upad;   // gathered: R_up (pass 1) / R_dn (pass 0)
     const size_t ooff = pass ? (size_t)a.wk.Upad : 0;   // written: v / u
@@ -991,7 +992,7 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
     const int r0 = (int)((int64_t)nrows * rs / rsplit);
     const int r1 = min((int)((int64_t)nrows * (rs + 1) / rsplit), nrows_eff);
     int *cj = Cj[wave];
-    double *cv = Cv[wave];
+    A *cv = Cv[wave];
     double part = 0.0;
     for (int c = 0; c < nch; ++c) {
         const int cb = c * CC;
@@ -1044,12 +1045,12 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                 const int ke = __builtin_amdgcn_readlane(kev, jr);
                 const size_t o = (size_t)w * RV + ooff + i;
                 // two independent sums: even / odd offsets in the row segment
-                double s = 0.0, s2 = 0.0;
-                if (c != 0 && active) s = (double)uv[o];
+                A s = 0, s2 = 0;
+                if (c != 0 && active) s = (A)uv[o];
                 for (int base = kb; base < ke; base += 64) {
                     const int cnt = min(64, ke - base);
                     int jl = 0;
-                    double vl = 0.0;
+                    A vl = 0;
                     if (lane < cnt) {
                         jl = (idx[base + lane] - cb) * kSpmmLd;
                         vl = val[base + lane];
@@ -1064,15 +1065,15 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
                         for (int u = 0; u < kSpmmGroup; ++u) gx[u] = G[cj[t + u] + lane];
 #pragma unroll
                         for (int u = 0; u < kSpmmGroup; u += 2) {
-                            s = fma(cv[t + u], (double)gx[u], s);
-                            s2 = fma(cv[t + u + 1], (double)gx[u + 1], s2);
+                            s = fma(cv[t + u], (A)gx[u], s);
+                            s2 = fma(cv[t + u + 1], (A)gx[u + 1], s2);
                         }
                     }
                     // tail: the same even/odd split by offset in the row, so
                     // that a shorter segment (entries skipped for an uneven
                     // batch, all zero) sums in exactly the same grouping
                     for (; t < cnt; ++t) {
-                        const double x = (double)G[cj[t] + lane];
+                        const A x = (A)G[cj[t] + lane];
                         if ((base - kb + t) & 1) s2 = fma(cv[t], x, s2);
                         else s = fma(cv[t], x, s);
                     }
@@ -2046,11 +2047,11 @@ hipError_t launch_core(const KernelArgs &a, hipStream_t st, hipEvent_t *ev, cons
     const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
     const dim3 gs((tiles + 7) / 8 * 8 * a.psi_nparts, 2), bs(64 * kSpmmWaves);
     if (a.precision == MDET_MIXED)
-        k_spmm<float, kSpmmCols32><<<gs, bs, 0, st>>>(
-            a, a.wk.R32, a.wk.R64, a.wk.uv32, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg32,
+        k_spmm<float, kSpmmCols32, float><<<gs, bs, 0, st>>>(
+            a, a.wk.R32, a.wk.R64, a.wk.uv32, a.C.rval32, a.C.cval32, a.C.rcol, a.C.crow, a.C.rseg32,
             a.C.cseg32, a.C.nch_r32, a.C.nch_c32, a.psi_nparts);
     else
-        k_spmm<double, kSpmmCols64><<<gs, bs, 0, st>>>(
+        k_spmm<double, kSpmmCols64, double><<<gs, bs, 0, st>>>(
             a, a.wk.R64, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
             a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
     mark(3, true, st);
@@ -2096,11 +2097,11 @@ hipError_t launch_chain(const KernelArgs &a, hipStream_t st, hipEvent_t *ev) {
     const int tiles = (W + kSpmmTile - 1) / kSpmmTile;
     const dim3 gs((tiles + 7) / 8 * 8 * a.psi_nparts, 2), bs(64 * kSpmmWaves);
     if (mixed)
-        k_spmm<float, kSpmmCols32><<<gs, bs, 0, st>>>(
-            a, a.wk.R32, a.wk.R64, a.wk.uv32, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg32,
+        k_spmm<float, kSpmmCols32, float><<<gs, bs, 0, st>>>(
+            a, a.wk.R32, a.wk.R64, a.wk.uv32, a.C.rval32, a.C.cval32, a.C.rcol, a.C.crow, a.C.rseg32,
             a.C.cseg32, a.C.nch_r32, a.C.nch_c32, a.psi_nparts);
     else
-        k_spmm<double, kSpmmCols64><<<gs, bs, 0, st>>>(
+        k_spmm<double, kSpmmCols64, double><<<gs, bs, 0, st>>>(
             a, a.wk.R64, a.wk.R64, a.wk.uv64, a.C.rval, a.C.cval, a.C.rcol, a.C.crow, a.C.rseg64,
             a.C.cseg64, a.C.nch_r64, a.C.nch_c64, a.psi_nparts);
     mark(3, true);

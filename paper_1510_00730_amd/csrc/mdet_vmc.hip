@@ -238,17 +238,53 @@ __device__ __forceinline__ double jump_weight(const double *r, double jref) {
     return jref > 0.0 ? 1.0 / (r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + jref * jref) : 1.0;
 }
 
-// Per-walker part of the training objective J = A sum_e c_e |r'_e - r_e|^2
-// (loss = -mean J, c_e = jump_weight): writes the output gradient of the
-// evaluation at R' (dO2, FP32), the direct gradient w.r.t. R' (gRp, FP64),
-// g_ell and the walker's J.
+// Coulomb potential energy of one configuration, point nucleus of charge Z at
+// the origin: V = -Z sum_e 1/|r_e| + sum_{e<f} 1/|r_e - r_f|; with dV (not
+// null) also its gradient dV[3e + ax].
+__device__ double coulomb_v(int N, double Z, const double *r, double *dV) {
+    double v = 0.0;
+    for (int e = 0; e < N; ++e) {
+        const double *re = r + 3 * e;
+        const double d2 = re[0] * re[0] + re[1] * re[1] + re[2] * re[2];
+        const double id = 1.0 / sqrt(d2);
+        v -= Z * id;
+        if (dV) {
+            const double c = Z * id * id * id;
+            for (int ax = 0; ax < 3; ++ax) dV[3 * e + ax] = c * re[ax];
+        }
+    }
+    for (int e = 0; e < N; ++e)
+        for (int f = e + 1; f < N; ++f) {
+            double d[3], d2 = 0.0;
+            for (int ax = 0; ax < 3; ++ax) {
+                d[ax] = r[3 * e + ax] - r[3 * f + ax];
+                d2 += d[ax] * d[ax];
+            }
+            const double id = 1.0 / sqrt(d2);
+            v += id;
+            if (dV) {
+                const double c = id * id * id;
+                for (int ax = 0; ax < 3; ++ax) {
+                    dV[3 * e + ax] -= c * d[ax];
+                    dV[3 * f + ax] += c * d[ax];
+                }
+            }
+        }
+    return v;
+}
+
+// Per-walker part of the training objective J = A jump (loss = -mean J),
+// jump = sum_e c_e |r'_e - r_e|^2 (objective 0, c_e = jump_weight) or
+// (V(R') - V(R))^2 (objective 1, the squared change of the potential energy):
+// writes the output gradient of the evaluation at R' (dO2, FP32), the direct
+// gradient w.r.t. R' (gRp, FP64), g_ell and the walker's J.
 __global__ void __launch_bounds__(kVBlock) k_esjd_head(int64_t W, int N, const double *R,
                                                        const double *Rp, const double *xi,
                                                        const double *logabsR, const double *signp,
                                                        const double *logabsp, const double *glp,
                                                        const float *o1, const float *o2, float *dO2,
                                                        double *gRp, double *gell, double *Jw,
-                                                       double jref) {
+                                                       double jref, int objective, double Z) {
     const int64_t w = (int64_t)blockIdx.x * kVBlock + threadIdx.x;
     if (w >= W) return;
     const int n3 = 3 * N, n4 = 4 * N;
@@ -271,6 +307,13 @@ __global__ void __launch_bounds__(kVBlock) k_esjd_head(int64_t W, int N, const d
         lq_fwd += -0.5 * x2 - 3.0 * ls;
         lq_rev += -0.5 * d2 * inv2 - 3.0 * ls2;
     }
+    // potential-energy objective: the gradient of V at R' goes to gRp first
+    // (scaled below), so no per-walker array beyond gRp is needed
+    double dv = 0.0;
+    if (objective == 1) {
+        dv = coulomb_v(N, Z, Rpw, gRp + w * n3) - coulomb_v(N, Z, Rw, nullptr);
+        jump = dv * dv;
+    }
     const bool node = signp[w] == 0.0;
     const double ell = node ? -INFINITY : 2.0 * (logabsp[w] - logabsR[w]) + lq_rev - lq_fwd;
     const double A = node ? 0.0 : (ell < 0.0 ? exp(ell) : 1.0);
@@ -288,7 +331,9 @@ __global__ void __launch_bounds__(kVBlock) k_esjd_head(int64_t W, int N, const d
         for (int ax = 0; ax < 3; ++ax) {
             const double d = Rw[3 * e + ax] - Rpw[3 * e + ax] - (double)a2[3 * e + ax];
             d2 += d * d;
-            const double g = gJ * A * 2.0 * ce * (Rpw[3 * e + ax] - Rw[3 * e + ax]) +
+            const double dj = objective == 1 ? 2.0 * dv * gRp[w * n3 + 3 * e + ax]
+                                             : 2.0 * ce * (Rpw[3 * e + ax] - Rw[3 * e + ax]);
+            const double g = gJ * A * dj +
                              ge * (2.0 * glp[w * n4 + 4 * e + ax] + d * inv2);
             gRp[w * n3 + 3 * e + ax] = g;
             dO2[w * n4 + 3 * e + ax] = (float)(ge * d * inv2);
@@ -448,9 +493,10 @@ void launch_mlp_propose(int64_t W, int N, const double *R, const float *o, const
 void launch_esjd_head(int64_t W, int N, const double *R, const double *Rp, const double *xi,
                       const double *logabsR, const double *signp, const double *logabsp,
                       const double *glp, const float *o1, const float *o2, float *dO2,
-                      double *gRp, double *gell, double *Jw, double jump_ref, hipStream_t st) {
+                      double *gRp, double *gell, double *Jw, double jump_ref, int objective,
+                      double Z, hipStream_t st) {
     k_esjd_head<<<g1(W), dim3(kVBlock), 0, st>>>(W, N, R, Rp, xi, logabsR, signp, logabsp, glp, o1,
-                                                  o2, dO2, gRp, gell, Jw, jump_ref);
+                                                  o2, dO2, gRp, gell, Jw, jump_ref, objective, Z);
 }
 
 void launch_esjd_chain(int64_t W, int N, const double *xi, const float *o1, const double *gRp,

@@ -46,11 +46,15 @@ def main(argv=None):
     ap.add_argument("--quick", action="store_true", help="small sizes (test)")
     ap.add_argument("--walkers", type=int, default=2048)
     ap.add_argument("--samples", type=int, default=1_000_000)
-    ap.add_argument("--train-iters", type=int, default=1500)
-    ap.add_argument("--compare-steps", type=int, default=2000)
+    ap.add_argument("--compare-steps", type=int, default=6000)
     ap.add_argument("--config", type=int, default=5)
-    ap.add_argument("--jump-refs", type=float, nargs="+", default=[0.0, 1.0, 0.3],
+    ap.add_argument("--jump-refs", type=float, nargs="+", default=[0.0, 4.0],
                     help="jump weightings to train (0: plain squared jump)")
+    ap.add_argument("--checkpoints", type=int, nargs="+", default=[100, 400, 1500],
+                    help="training iterations at which the network is compared")
+    ap.add_argument("--potential", action="store_true",
+                    help="also train on the jump of the potential energy")
+    ap.add_argument("--lr", type=float, default=1e-3)
     args = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if root not in sys.path:
@@ -59,11 +63,12 @@ def main(argv=None):
 
     from gen.workloads import make_config, mlp_init
     from . import Evaluator
-    from .binding import PROP_GAUSSIAN, PROP_MLP
-    from .vmc import Walkers, run, tau_int, train_proposal
+    from .binding import OBJ_JUMP, OBJ_POTENTIAL, PROP_GAUSSIAN, PROP_MLP
+    from .vmc import Walkers, run, tau_int, tau_int_walkers, train_proposal
 
     if args.quick:
-        args.walkers, args.samples, args.train_iters, args.compare_steps = 512, 60_000, 200, 300
+        args.walkers, args.samples, args.compare_steps = 512, 60_000, 300
+        args.checkpoints = [50, 200]
     wl = make_config(args.config, n_walk=args.walkers)
     ev = Evaluator(0)
     ev.load_workload(wl)
@@ -91,32 +96,48 @@ def main(argv=None):
         snaps.append(w.R.float().cpu().numpy())
     samples = np.concatenate(snaps).astype(np.float64)
     out["training_samples"] = int(samples.shape[0])
-    # 3. training, one network per jump weighting
+    # 3. training, one network per jump weighting, kept at a few points of
+    #    its training (checkpoints)
     p0 = mlp_init(3 * N, H, 4 * N, seed=7)
     nets = {}
-    for ref in args.jump_refs:
+    objectives = [(f"jump_ref={ref:g}", OBJ_JUMP, ref) for ref in args.jump_refs]
+    if args.potential:
+        objectives.append(("potential", OBJ_POTENTIAL, 0.0))
+    for oname, obj, ref in objectives:
         t0 = time.perf_counter()
-        params, losses = train_proposal(ev, samples, p0, H, args.train_iters, min(2048, W),
-                                        lr=1e-3, jump_ref=ref)
-        nets[ref] = params
-        out.setdefault("training", {})[f"jump_ref={ref:g}"] = {
+        params, done, losses, state = p0, 0, [], {}
+        for ck in sorted(args.checkpoints):
+            params, ls = train_proposal(ev, samples, params, H, ck - done, min(2048, W),
+                                        lr=args.lr, jump_ref=ref, seed=5, state=state,
+                                        objective=obj, nuclear_charge=N)
+            params = params.cpu().numpy()
+            losses.extend(ls.tolist())
+            done = ck
+            nets[(oname, ck)] = params
+        out.setdefault("training", {})[oname] = {
             "seconds": time.perf_counter() - t0,
             "loss_first_last": [float(np.mean(losses[:20])), float(np.mean(losses[-20:]))]}
     # 4. comparison from the same equilibrated walkers
     R_eq = w.R.cpu().numpy()
     res = {}
     runs = [(f"gaussian_step={s:g}", PROP_GAUSSIAN, s, None) for s in grid]
-    runs += [(f"mlp_jump_ref={ref:g}", PROP_MLP, 0.0, (nets[ref], H)) for ref in args.jump_refs]
+    runs += [(f"mlp_{oname}_iters={ck}", PROP_MLP, 0.0,
+              (torch.as_tensor(p, dtype=torch.float32, device="cuda"), H))
+             for (oname, ck), p in nets.items()]
     for name, prop, stp, mlp in runs:
         wk = Walkers(ev, R_eq, seed=202)
         run(wk, 50, prop, stp, mlp, record=False)
         jd = esjd_of(wk, run, 50, prop, stp, mlp)
-        el, r2, acc, dt = run(wk, args.compare_steps, prop, stp, mlp)
-        t_el, t_r2 = tau_int(el), tau_int(r2)
+        el, r2, acc, dt, (elw, r2w) = run(wk, args.compare_steps, prop, stp, mlp,
+                                          per_walker=True)
+        t_el, t_r2 = tau_int_walkers(elw), tau_int_walkers(r2w)
+        t_el_avg = tau_int(el)
+        del elw, r2w
         rate = W * args.compare_steps / dt
         res[name] = {"acceptance": float(acc.mean()), "esjd": jd,
                      "ms_per_step": 1e3 * dt / args.compare_steps,
-                     "tau_int_E_L": t_el, "tau_int_sum_r2": t_r2, "mean_E_L": float(np.mean(el)),
+                     "tau_int_E_L": t_el, "tau_int_sum_r2": t_r2,
+                     "tau_int_E_L_from_averaged_series": t_el_avg, "mean_E_L": float(np.mean(el)),
                      "err_E_L": float(np.std(el) * np.sqrt(t_el / el.size)),
                      "mean_sum_r2": float(np.mean(r2)),
                      "effective_samples_per_s_E_L": rate / t_el,

@@ -144,12 +144,14 @@ def test_mlp_vmc_step_matches_reference(c2):
     np.testing.assert_allclose(Rt.cpu().numpy()[clear], Rnew[clear], rtol=0, atol=1e-5)
 
 
-@pytest.mark.parametrize("H,jump_ref", [(32, 0.0), (128, 0.0), (128, 0.5)])
-def test_training_step_gradient_matches_reference(c2, H, jump_ref):
-    """Loss and parameter gradient of the jump objective vs the exact FP64 one
-    (which the CPU tests pin by finite differences), at a small width and at
-    the production width 128, plain and with the relative jump weighting."""
-    log(f"[vmc] MLP training step gradient, H={H}, jump_ref {jump_ref}")
+@pytest.mark.parametrize("H,jump_ref,objective", [(32, 0.0, 0), (128, 0.0, 0), (128, 0.5, 0),
+                                                  (128, 0.0, 1)])
+def test_training_step_gradient_matches_reference(c2, H, jump_ref, objective):
+    """Loss and parameter gradient of the training objective vs the exact FP64
+    one (which the CPU tests pin by finite differences), at a small width and
+    at the production width 128: plain and weighted jumps, and the jump of the
+    potential energy."""
+    log(f"[vmc] MLP training step gradient, H={H}, jump_ref {jump_ref}, objective {objective}")
     wl, ev = c2
     W, N = 64, wl.n_elec
     p = mlp_init(3 * N, H, 4 * N, seed=12)
@@ -160,7 +162,8 @@ def test_training_step_gradient_matches_reference(c2, H, jump_ref):
     v = torch.zeros_like(pt)
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     grad = torch.empty_like(pt)
-    ev.mlp_train_step(pt, m, v, 1, 1e-6, dev(R), dev(xi), H, loss, grad=grad, jump_ref=jump_ref)
+    ev.mlp_train_step(pt, m, v, 1, 1e-6, dev(R), dev(xi), H, loss, grad=grad, jump_ref=jump_ref,
+                      objective=objective, nuclear_charge=N)
     torch.cuda.synchronize()
 
     def psi_fn(Rp):
@@ -169,7 +172,7 @@ def test_training_step_gradient_matches_reference(c2, H, jump_ref):
     lR = oracle.evaluate(wl, R, n_threads=16).logabs
     # the network sees FP32 inputs on the device
     rl, rg, info = omlp.esjd_loss_and_grad(p.astype(np.float64), R, xi, lR, psi_fn, H,
-                                           jump_ref=jump_ref)
+                                           jump_ref=jump_ref, objective=objective, Z=float(N))
     g = grad.cpu().numpy()
     log(f"loss gpu {float(loss):.6e} ref {rl:.6e}; |g-gref|/|gref| "
         f"{np.linalg.norm(g - rg) / np.linalg.norm(rg):.2e}; min |ell| {np.abs(info['ell']).min():.2e}")

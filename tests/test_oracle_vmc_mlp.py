@@ -73,8 +73,28 @@ def _gaussian_psi(alpha):
     return fn
 
 
-@pytest.mark.parametrize("jump_ref", [0.0, 0.7])
-def test_esjd_gradient_finite_differences(jump_ref):
+def test_coulomb_potential_closed_form_and_gradient():
+    # two electrons on the x axis at 1 and 3 around charge 2: V = -2 (1 + 1/3) + 1/2
+    R = np.array([[[1.0, 0.0, 0.0], [3.0, 0.0, 0.0]]])
+    V, g = mlp.coulomb_potential(R, 2.0)
+    assert abs(V[0] - (-2.0 * (1 + 1 / 3) + 0.5)) < 1e-15
+    # dV/dx1 = 2 x1/|x1|^3 - (x1 - x2)/|x1 - x2|^3 = 2 + 1/4, dV/dx2 = 2/9 - 1/4
+    assert abs(g[0, 0, 0] - (2.0 + 0.25)) < 1e-14 and abs(g[0, 1, 0] - (2.0 / 9 - 0.25)) < 1e-14
+    # finite differences on a random configuration
+    rng = np.random.default_rng(7)
+    R = rng.normal(0, 1.5, (2, 5, 3))
+    V, g = mlp.coulomb_potential(R, 3.0)
+    h = 1e-6
+    for (b, e, ax) in ((0, 1, 2), (1, 4, 0), (1, 0, 1)):
+        Rp, Rm = R.copy(), R.copy()
+        Rp[b, e, ax] += h
+        Rm[b, e, ax] -= h
+        fd = (mlp.coulomb_potential(Rp, 3.0)[0][b] - mlp.coulomb_potential(Rm, 3.0)[0][b]) / (2 * h)
+        assert abs(fd - g[b, e, ax]) < 1e-6 * (1 + abs(fd))
+
+
+@pytest.mark.parametrize("jump_ref,objective", [(0.0, 0), (0.7, 0), (0.0, 1)])
+def test_esjd_gradient_finite_differences(jump_ref, objective):
     N, n_hid, B = 3, 6, 5
     n_in, n_out = 3 * N, 4 * N
     p = _params(n_in, n_hid, n_out, 3, scale=0.2)
@@ -83,17 +103,22 @@ def test_esjd_gradient_finite_differences(jump_ref):
     xi = r.normal(0, 1.0, (B, N, 3))
     psi = _gaussian_psi(0.4)
     lR = psi(R)[0]
-    loss, g, info = mlp.esjd_loss_and_grad(p, R, xi, lR, psi, n_hid, jump_ref=jump_ref)
+    kw = dict(jump_ref=jump_ref, objective=objective, Z=3.0)
+    loss, g, info = mlp.esjd_loss_and_grad(p, R, xi, lR, psi, n_hid, **kw)
     assert np.all(np.abs(info["ell"]) > 1e-3)      # no walker on the min(1, .) kink
-    # the objective itself: A times the (weighted) squared jumps, written out
-    c = 1.0 if jump_ref <= 0 else 1.0 / (np.sum(R * R, axis=2) + jump_ref ** 2)
-    J = info["A"] * np.sum(c * np.sum((info["Rp"] - R) ** 2, axis=2), axis=1)
+    # the objective itself, written out
+    if objective == 0:
+        c = 1.0 if jump_ref <= 0 else 1.0 / (np.sum(R * R, axis=2) + jump_ref ** 2)
+        J = info["A"] * np.sum(c * np.sum((info["Rp"] - R) ** 2, axis=2), axis=1)
+    else:
+        J = info["A"] * (mlp.coulomb_potential(info["Rp"], 3.0)[0]
+                         - mlp.coulomb_potential(R, 3.0)[0]) ** 2
     assert abs(loss + J.mean()) < 1e-14 * abs(loss)
     h = 1e-6
     for i in r.choice(p.size, 25, replace=False):
         e = np.zeros_like(p); e[i] = h
-        lp = mlp.esjd_loss_and_grad(p + e, R, xi, lR, psi, n_hid, jump_ref=jump_ref)[0]
-        lm = mlp.esjd_loss_and_grad(p - e, R, xi, lR, psi, n_hid, jump_ref=jump_ref)[0]
+        lp = mlp.esjd_loss_and_grad(p + e, R, xi, lR, psi, n_hid, **kw)[0]
+        lm = mlp.esjd_loss_and_grad(p - e, R, xi, lR, psi, n_hid, **kw)[0]
         fd = (lp - lm) / (2 * h)
         assert abs(fd - g[i]) < 2e-6 * (1 + abs(fd)), (i, fd, g[i])
 
@@ -147,3 +172,21 @@ def test_metropolis_samples_the_square_of_psi(proposal, step):
     err = blocks.std(ddof=1) / math.sqrt(blocks.size)
     assert abs(x2.mean() - 1 / (4 * a)) < 4 * err + 2e-3
     assert 0.2 < np.mean(acc) < 0.99
+
+
+def test_tau_int_walkers_ar1():
+    """tau_int of a walker average from per-walker autocovariances, against
+    the closed form (1 + phi) / (1 - phi) of AR(1) chains."""
+    import torch
+    from paper_1510_00730_amd.vmc import tau_int_walkers
+    rng = np.random.default_rng(3)
+    for phi in (0.0, 0.5, 0.9):
+        n, W = 4000, 256
+        x = np.zeros((n, W))
+        z = rng.normal(size=(n, W))
+        x[0] = z[0] / np.sqrt(1 - phi * phi)
+        for t in range(1, n):
+            x[t] = phi * x[t - 1] + z[t]
+        tau = tau_int_walkers(torch.as_tensor(x))
+        exact = (1 + phi) / (1 - phi)
+        assert abs(tau - exact) < 0.08 * exact + 0.05, (phi, tau, exact)
