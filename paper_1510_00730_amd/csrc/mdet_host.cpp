@@ -74,20 +74,20 @@ struct SpinHost {
     int64_t n_by_degree[MDET_MAX_DEGREE + 1] = {0};
     bool high_degree = false;  // some determinant above MDET_MAX_DEGREE (chain method only)
     int64_t n_above = 0;
-    std::vector<int32_t> adj_off, chunk_det, gptr;
-    std::vector<uint16_t> gpos;
+    std::vector<int32_t> adj_off, chunk_det;
+    std::vector<uint32_t> gent;
     // Sherman-Morrison chain lists (public order = chain order)
     std::vector<int32_t> sm_exec, sm_off;
     std::vector<uint16_t> sm_occ;
     std::vector<uint32_t> sm_sub;
-    DevBuf d_occ0, d_desc, d_adj_off, d_chunk_det, d_gptr, d_gpos;
+    DevBuf d_occ0, d_desc, d_adj_off, d_chunk_det, d_gent;
     DevBuf d_sm_exec, d_sm_occ, d_sm_off, d_sm_sub, d_desc_hi, d_hi_off;
-    std::array<DevBuf *, 12> bufs() {
-        return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gptr, &d_gpos,
+    std::array<DevBuf *, 11> bufs() {
+        return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gent,
                 &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub, &d_desc_hi, &d_hi_off};
     }
-    std::array<const DevBuf *, 12> bufs() const {
-        return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gptr, &d_gpos,
+    std::array<const DevBuf *, 11> bufs() const {
+        return {&d_occ0, &d_desc, &d_adj_off, &d_chunk_det, &d_gent,
                 &d_sm_exec, &d_sm_occ, &d_sm_off, &d_sm_sub, &d_desc_hi, &d_hi_off};
     }
 };
@@ -447,8 +447,7 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
     if (s.high_degree) {  // no table-method structures: one empty cofactor chunk
         s.adj_off.assign(s.U + 1, 0);
         s.chunk_det.assign({0, (int32_t)s.U});
-        s.gptr.assign((size_t)n * n_mo + 1, 0);
-        s.gpos.assign(1, 0);
+        s.gent.assign((size_t)kBlockThreads * kGent, kGentNone);
         s.desc_hi.clear();
         s.hi_off.assign(1, 0);
         return;
@@ -456,42 +455,78 @@ void analyse_spin(SpinHost &s, int n_int, int n_mo) {
     // Derivative aggregation: the s*s scaled cofactor entries of determinant d
     // occupy slots adj_off[d] + a*s + b of a staging buffer; determinants are
     // cut into chunks of at most kAdjChunkDets determinants whose slots fit
-    // kAdjChunk; per chunk, every target
-    // t = h[a]*M + p[b] gets the list of its slots (in determinant order).
+    // kAdjChunk.  Per chunk, the targets t = h[a]*M + p[b] are dealt to the
+    // kBlockThreads threads of the aggregating block (largest list first, to
+    // the least loaded thread), each thread getting at most kGent entries: a
+    // thread adds the staged slots of its targets, so no target is shared and
+    // the sums need no atomics.  gent[chunk][thread][i] = slot | t << 16,
+    // sorted by target, then determinant order; kGentNone pads.
     s.adj_off.assign(s.U + 1, 0);
     for (int64_t e = 0; e < s.U; ++e) s.adj_off[e + 1] = s.adj_off[e] + ex[e].s * ex[e].s;
-    s.chunk_det.assign(1, 0);
-    for (int64_t e = 0; e < s.U; ++e)
-        if (s.adj_off[e + 1] - s.adj_off[s.chunk_det.back()] > kAdjChunk ||
-            e - s.chunk_det.back() >= kAdjChunkDets)
-            s.chunk_det.push_back((int32_t)e);
-    s.chunk_det.push_back((int32_t)s.U);
-    const int nchunk = (int)s.chunk_det.size() - 1;
     const int64_t nt = (int64_t)n * n_mo;
-    s.gptr.assign((size_t)nchunk * (nt + 1), 0);
-    s.gpos.assign(s.adj_off[s.U], 0);
-    int64_t filled = 0;
-    for (int k = 0; k < nchunk; ++k) {
-        int32_t *gp = s.gptr.data() + (size_t)k * (nt + 1);
-        const int32_t base = s.adj_off[s.chunk_det[k]];
-        std::vector<int32_t> cnt(nt + 1, 0);
-        for (int64_t e = s.chunk_det[k]; e < s.chunk_det[k + 1]; ++e) {
-            const Exc &X = ex[e];
-            for (int a = 0; a < X.s; ++a)
-                for (int b = 0; b < X.s; ++b) cnt[(int64_t)X.h[a] * n_mo + X.p[b] + 1]++;
+    if (nt >= (int64_t)kGentNone >> 16) throw std::runtime_error("electrons x orbitals too large");
+    s.chunk_det.assign(1, 0);
+    s.gent.clear();
+    std::vector<int32_t> cnt(nt, 0), load(kBlockThreads), owner(nt, -1);
+    std::vector<int64_t> targets;
+    int64_t start = 0;
+    while (start < s.U) {
+        int64_t end = start;
+        while (end < s.U && end - start < kAdjChunkDets &&
+               s.adj_off[end + 1] - s.adj_off[start] <= kAdjChunk)
+            ++end;
+        if (end == start) throw std::runtime_error("cofactor entries of one determinant exceed the staging buffer");
+        for (;;) {
+            // entries per target, then largest-first assignment
+            targets.clear();
+            for (int64_t e = start; e < end; ++e)
+                for (int a = 0; a < ex[e].s; ++a)
+                    for (int b = 0; b < ex[e].s; ++b) {
+                        const int64_t tt = (int64_t)ex[e].h[a] * n_mo + ex[e].p[b];
+                        if (cnt[tt]++ == 0) targets.push_back(tt);
+                    }
+            std::stable_sort(targets.begin(), targets.end(),
+                             [&](int64_t x, int64_t y) { return cnt[x] > cnt[y]; });
+            std::fill(load.begin(), load.end(), 0);
+            int32_t worst = 0;
+            for (int64_t tt : targets) {
+                const int j = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                owner[tt] = j;
+                load[j] += cnt[tt];
+                worst = std::max(worst, load[j]);
+            }
+            if (worst <= kGent || end == start + 1) break;
+            for (int64_t tt : targets) cnt[tt] = 0, owner[tt] = -1;
+            end = start + std::max<int64_t>(1, (end - start) * 9 / 10);
         }
-        gp[0] = (int32_t)filled;
-        for (int64_t t = 0; t < nt; ++t) gp[t + 1] = gp[t] + cnt[t + 1];
-        std::vector<int32_t> fill(gp, gp + nt);
-        for (int64_t e = s.chunk_det[k]; e < s.chunk_det[k + 1]; ++e) {
-            const Exc &X = ex[e];
-            for (int a = 0; a < X.s; ++a)
-                for (int b = 0; b < X.s; ++b) {
-                    const int64_t t = (int64_t)X.h[a] * n_mo + X.p[b];
-                    s.gpos[fill[t]++] = (uint16_t)(s.adj_off[e] - base + a * X.s + b);
+        // the chunk's lists: per thread, its targets ascending, each target's
+        // slots in determinant order
+        const size_t base = s.gent.size();
+        s.gent.resize(base + (size_t)kBlockThreads * kGent, kGentNone);
+        std::vector<std::vector<std::pair<int64_t, int32_t>>> per(kBlockThreads);
+        const int32_t slot0 = s.adj_off[start];
+        for (int64_t e = start; e < end; ++e)
+            for (int a = 0; a < ex[e].s; ++a)
+                for (int b = 0; b < ex[e].s; ++b) {
+                    const int64_t tt = (int64_t)ex[e].h[a] * n_mo + ex[e].p[b];
+                    per[owner[tt]].push_back({tt, s.adj_off[e] - slot0 + a * ex[e].s + b});
                 }
+        for (int j = 0; j < kBlockThreads; ++j) {
+            auto &v = per[j];
+            if ((int)v.size() > kGent) throw std::runtime_error("cofactor list exceeds its thread");
+            std::stable_sort(v.begin(), v.end(),
+                             [](const std::pair<int64_t, int32_t> &x,
+                                const std::pair<int64_t, int32_t> &y) { return x.first < y.first; });
+            for (size_t i = 0; i < v.size(); ++i)
+                s.gent[base + (size_t)j * kGent + i] = (uint32_t)v[i].second | ((uint32_t)v[i].first << 16);
         }
-        filled = gp[nt];
+        for (int64_t tt : targets) cnt[tt] = 0, owner[tt] = -1;
+        s.chunk_det.push_back((int32_t)end);
+        start = end;
+    }
+    if (s.chunk_det.size() == 1) {  // no determinants: one empty chunk
+        s.chunk_det.push_back((int32_t)s.U);
+        s.gent.assign((size_t)kBlockThreads * kGent, kGentNone);
     }
 }
 
@@ -776,8 +811,7 @@ void enqueue_eval(mdet_ctx *ctx, int64_t n_walk, const double *R_dev, int32_t pr
         d.hi_off = ctx->sp[s].d_hi_off.as<int32_t>();
         d.adj_off = ctx->sp[s].d_adj_off.as<int32_t>();
         d.chunk_det = ctx->sp[s].d_chunk_det.as<int32_t>();
-        d.gptr = ctx->sp[s].d_gptr.as<int32_t>();
-        d.gpos = ctx->sp[s].d_gpos.as<uint16_t>();
+        d.gent = ctx->sp[s].d_gent.as<uint32_t>();
         d.sm_exec = ctx->sp[s].d_sm_exec.as<int32_t>();
         d.sm_occ = ctx->sp[s].d_sm_occ.as<uint16_t>();
         d.sm_off = ctx->sp[s].d_sm_off.as<int32_t>();
@@ -1095,8 +1129,7 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             sp[s].d_desc.upload(sp[s].desc);
             sp[s].d_adj_off.upload(sp[s].adj_off);
             sp[s].d_chunk_det.upload(sp[s].chunk_det);
-            sp[s].d_gptr.upload(sp[s].gptr);
-            sp[s].d_gpos.upload(sp[s].gpos);
+            sp[s].d_gent.upload(sp[s].gent);
             sp[s].d_sm_exec.upload(sp[s].sm_exec);
             sp[s].d_sm_occ.upload(sp[s].sm_occ);
             sp[s].d_sm_off.upload(sp[s].sm_off);
@@ -1142,14 +1175,12 @@ mdet_status mdet_set_expansion(mdet_ctx *ctx, int32_t n_up, int32_t n_dn, int32_
             ctx->sp[s].n_above = sp[s].n_above;
             ctx->sp[s].adj_off.swap(sp[s].adj_off);
             ctx->sp[s].chunk_det.swap(sp[s].chunk_det);
-            ctx->sp[s].gptr.swap(sp[s].gptr);
-            ctx->sp[s].gpos.swap(sp[s].gpos);
+            ctx->sp[s].gent.swap(sp[s].gent);
             std::swap(ctx->sp[s].d_occ0, sp[s].d_occ0);
             std::swap(ctx->sp[s].d_desc, sp[s].d_desc);
             std::swap(ctx->sp[s].d_adj_off, sp[s].d_adj_off);
             std::swap(ctx->sp[s].d_chunk_det, sp[s].d_chunk_det);
-            std::swap(ctx->sp[s].d_gptr, sp[s].d_gptr);
-            std::swap(ctx->sp[s].d_gpos, sp[s].d_gpos);
+            std::swap(ctx->sp[s].d_gent, sp[s].d_gent);
             ctx->sp[s].sm_exec.swap(sp[s].sm_exec);
             ctx->sp[s].sm_occ.swap(sp[s].sm_occ);
             ctx->sp[s].sm_off.swap(sp[s].sm_off);

@@ -47,10 +47,15 @@ static_assert(sizeof(DetDescHi) == 32, "DetDescHi layout");
 
 // Capacity (doubles) of the LDS staging buffer that holds the scaled
 // adjugates of one chunk of determinants during the derivative aggregation.
-constexpr int kAdjChunk = 2048;
-// Largest number of determinants in one such chunk (two per thread of the
-// 256-thread derivative block).
-constexpr int kAdjChunkDets = 512;
+constexpr int kAdjChunk = 3072;
+// Threads of the derivative-aggregation block.
+constexpr int kBlockThreads = 256;
+// Largest number of determinants in one such chunk (three per thread).
+constexpr int kAdjChunkDets = 768;
+// Staged entries one thread adds per chunk (its targets' lists), and the
+// padding of a thread's list.
+constexpr int kGent = 16;
+constexpr uint32_t kGentNone = 0xFFFFFFFFu;
 // Sparse combination: a tile of 64 walkers (one per lane) stages the
 // gathered vector in LDS by chunks of kSpmmCols64 (FP64) or kSpmmCols32
 // (FP32) entries, 130 KB either way (row pitch 65).
@@ -74,8 +79,10 @@ struct SpinDev {
     const int32_t *hi_off;     // [U - deg_end[kFastDegree] + 1]
     const int32_t *adj_off;    // [U+1] first adjugate slot of each determinant (sum of s^2)
     const int32_t *chunk_det;  // [nchunk+1] determinant range of each chunk
-    const int32_t *gptr;       // [nchunk][n*M+1] per-chunk gather lists, target t = c*M + m
-    const uint16_t *gpos;      // adjugate slot (chunk-local) of each list entry
+    // [nchunk][kBlockThreads][kGent] per chunk and thread, the staged slots
+    // the thread adds: chunk-local slot | target t << 16 (t = c*M + m), sorted
+    // by target; kGentNone pads
+    const uint32_t *gent;
     // Sherman-Morrison chain (Sec. 2.2): the distinct determinants in the
     // sorted order of Eq. (comp), position i -> execution index sm_exec[i]
     const int32_t *sm_exec;    // [U]

@@ -1102,20 +1102,24 @@ __global__ void __launch_bounds__(64 * kSpmmWaves)
 
 // ---------------------------------------------------------------------------
 // K6: derivative aggregation (table method).  Per chunk of determinants the
-// scaled adjugates w_d f_d adj(M_d) are staged in LDS, then every target
-// (slot c, orbital m) sums its slots in a fixed order into Gamma[c][m].
+// scaled adjugates w_d f_d adj(M_d) are staged in LDS, then every thread adds
+// the staged slots of the targets (slot c, orbital m) it owns in this chunk,
+// in a fixed order, into Gamma[c][m]: no target has two owners, so the sums
+// are deterministic without atomics.
 // ---------------------------------------------------------------------------
 // LDS layout of k_deriv: T [n][M], X [n][n], Gam [n][M], then a region used
-// first by the chunk loop (adjugates cb [kAdjChunk], gather pointers
-// [n*M + 1], gather positions [kAdjChunk]) and afterwards by Y [M][n],
-// Zc [n][n] and kDerivScratch partial sums; then Ex [M] and occ0 [n].
+// first by the chunk loop (adjugates cb [kAdjChunk]) and afterwards by
+// Y [M][n], Zc [n][n] and kDerivScratch partial sums; then Ex [M] and
+// occ0 [n].
 constexpr int kDerivScratch = 4 * 256;  // the waves' 16 x 16 partial blocks of Zc
 static_assert(kDerivScratch >= (kBlock / 64) * 256, "Zc partials");
-constexpr int kGpReg = 4;                   // gather pointers per thread held in registers
-constexpr int kGqReg = kAdjChunk / 256;     // gather positions per thread (all of them)
+static_assert(kDerivScratch >= kBlock + 2 * kPsiParts, "s1 partials and the psi partial sums");
+static_assert(kBlock == kBlockThreads, "gather lists are dealt to the block's threads");
+static_assert(kGent % 4 == 0, "gather lists are loaded 16 bytes at a time");
+constexpr int kS1Pre = 16;  // derivative-table values per thread loaded ahead of the s1 sums
 
 __host__ __device__ inline size_t deriv_union_doubles(int n, int M) {
-    const size_t loop = kAdjChunk + ((size_t)n * M + 1 + 1) / 2 + kAdjChunk / 4 + 1;
+    const size_t loop = kAdjChunk;
     const size_t tail = (size_t)M * n + (size_t)n * n + kDerivScratch;
     return loop > tail ? loop : tail;
 }
@@ -1133,35 +1137,25 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
     double *Gam = X + n * n;          // [n][M]  Gamma[c][m]
     double *un = Gam + nt;            // union region
     double *cb = un;                  // [kAdjChunk] staged adjugates
-    int *gpl = (int *)(cb + kAdjChunk);           // [n*M + 1] the chunk's gather pointers
-    uint16_t *gpo = (uint16_t *)(gpl + nt + 1);   // [kAdjChunk] the chunk's gather positions
     double *Y = un;                   // [M][n]   (after the chunk loop)
     double *Zc = Y + (size_t)M * n;   // [n][n]
     double *scr = Zc + n * n;         // [kDerivScratch]
     int *Ex = (int *)(un + deriv_union_doubles(n, M));  // [M]
     int *occ0 = Ex + M;               // [n]
     const double *phis = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
-    double col0[kKSteps];
-    pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
-               occ0, col0);
-    for (int i = tid; i < nt; i += kBlock) Gam[i] = 0.0;
-    __syncthreads();
-    build_table(phis, n, M, Ex, X, T, tid, kBlock, col0);
-    __syncthreads();
-    const int K = a.wk.K[ws];
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const bool mixed = a.precision == MDET_MIXED;
     // a chunk holds at most kDetsPerThread * kBlock determinants: thread tid
-    // takes the chunk's determinants tid + j * kBlock.  Their descriptors and
-    // weights and the thread's share of the chunk's gather lists are fetched
-    // one chunk ahead (registers).
+    // stages the chunk's determinants tid + j * kBlock and then adds the
+    // staged slots of its own targets (at most kGent).  The descriptors and
+    // weights of the next chunk are fetched while this chunk's targets are
+    // summed, its gather list right after (registers).
     constexpr int kDetsPerThread = kAdjChunkDets / kBlock;
     DetDesc Dc[kDetsPerThread];
     double wc[kDetsPerThread];
     int oc[kDetsPerThread];
     int hx[kDetsPerThread];  // degree above kFastDegree: exponent of the column scales
-    int gpr[kGpReg];
-    uint16_t gqr[kGqReg];
+    uint32_t ge[kGent];
     const int Ulo = S.deg_end[kFastDegree];
     auto fetch = [&](int k) {
         const int dk = S.chunk_det[k], d1 = S.chunk_det[k + 1];
@@ -1183,66 +1177,96 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
                 }
             }
         }
-        const int32_t *gp = S.gptr + (size_t)k * (nt + 1);
-        const int q0 = gp[0], nq = S.adj_off[d1] - base;
+    };
+    auto fetch_gather = [&](int k) {
+        const uint4 *g = reinterpret_cast<const uint4 *>(S.gent + ((size_t)k * kBlock + tid) * kGent);
 #pragma unroll
-        for (int j = 0; j < kGpReg; ++j) {
-            const int t = tid + j * kBlock;
-            gpr[j] = 0;
-            if (t <= nt) gpr[j] = gp[t] - q0;
-        }
-#pragma unroll
-        for (int j = 0; j < kGqReg; ++j) {
-            const int q = tid + j * kBlock;
-            gqr[j] = 0;
-            if (q < nq) gqr[j] = S.gpos[q0 + q];
+        for (int j = 0; j < kGent / 4; ++j) {
+            const uint4 v = g[j];
+            ge[4 * j] = v.x;
+            ge[4 * j + 1] = v.y;
+            ge[4 * j + 2] = v.z;
+            ge[4 * j + 3] = v.w;
         }
     };
+    double col0[kKSteps];
+    pair_setup(a.wk.X + ws * a.nmax * a.nmax, a.wk.E + ws * M, S.occ0, phis, n, M, tid, X, Ex,
+               occ0, col0);
+    const int K = a.wk.K[ws];
     fetch(0);
+    fetch_gather(0);
+    for (int i = tid; i < nt; i += kBlock) Gam[i] = 0.0;
+    __syncthreads();
+    build_table(phis, n, M, Ex, X, T, tid, kBlock, col0);
+    __syncthreads();
     for (int k = 0; k < S.nchunk; ++k) {
-        // the chunk's gather lists into LDS (beyond kGpReg * kBlock pointers:
-        // read here)
-        {
-            const int32_t *gp = S.gptr + (size_t)k * (nt + 1);
-            const int q0 = gp[0];
-#pragma unroll
-            for (int j = 0; j < kGpReg; ++j) {
-                const int t = tid + j * kBlock;
-                if (t <= nt) gpl[t] = gpr[j];
-            }
-            for (int t = tid + kGpReg * kBlock; t <= nt; t += kBlock) gpl[t] = gp[t] - q0;
-#pragma unroll
-            for (int j = 0; j < kGqReg; ++j) gpo[tid + j * kBlock] = gqr[j];
-        }
-#pragma unroll
+        // one determinant per pass, the thread's registers shifted down after
+        // each (one inlined copy of the staging code)
+#pragma unroll 1
         for (int j = 0; j < kDetsPerThread; ++j) {
-            const DetDesc &D = Dc[j];
+            const DetDesc D = Dc[0];
             const int s = D.s;
-            if (s == 0) continue;
-            double *dst = cb + oc[j];
+            double *dst = cb + oc[0];
             if (s > kFastDegree) {  // cofactors left by k_ratios_hi
                 const int d = S.chunk_det[k] + tid + j * kBlock;
                 stage_hi(a.wk.adjhi + ws * a.wk.hi_stride + S.hi_off[d - Ulo], s,
-                         (s <= dmax) ? wc[j] * (double)D.eps * pow2(hx[j] - K) : 0.0, dst);
-                continue;
+                         (s <= dmax) ? wc[0] * (double)D.eps * pow2(hx[0] - K) : 0.0, dst);
+            } else if (s > 0) {
+                const double wd = (s <= dmax) ? wc[0] * (double)D.eps : 0.0;
+                switch (s) {
+                case 1: stage_adj<1>(D, T, M, wd * pow2(delta_exponent_t<1>(D, Ex, occ0) - K), dst); break;
+                case 2: stage_adj<2>(D, T, M, wd * pow2(delta_exponent_t<2>(D, Ex, occ0) - K), dst); break;
+                case 3: stage_adj<3>(D, T, M, wd * pow2(delta_exponent_t<3>(D, Ex, occ0) - K), dst); break;
+                default: stage_adj<4>(D, T, M, wd * pow2(delta_exponent_t<4>(D, Ex, occ0) - K), dst); break;
+                }
             }
-            const double coef =
-                (s <= dmax) ? wc[j] * (double)D.eps * pow2(delta_exponent(D, Ex, occ0) - K) : 0.0;
-            switch (s) {
-            case 1: stage_adj<1>(D, T, M, coef, dst); break;
-            case 2: stage_adj<2>(D, T, M, coef, dst); break;
-            case 3: stage_adj<3>(D, T, M, coef, dst); break;
-            default: stage_adj<4>(D, T, M, coef, dst); break;
+#pragma unroll
+            for (int i = 0; i + 1 < kDetsPerThread; ++i) {
+                Dc[i] = Dc[i + 1];
+                wc[i] = wc[i + 1];
+                oc[i] = oc[i + 1];
+                hx[i] = hx[i + 1];
             }
         }
         __syncthreads();
         if (k + 1 < S.nchunk) fetch(k + 1);
-        for (int t = tid; t < nt; t += kBlock) {
-            double g = 0.0;
-            for (int q = gpl[t]; q < gpl[t + 1]; ++q) g += cb[gpo[q]];
-            Gam[t] += g;
+        // this thread's targets: all staged values read first, then summed per
+        // target in list order
+        {
+            double v[kGent];
+#pragma unroll
+            for (int i = 0; i < kGent; ++i) v[i] = ge[i] != kGentNone ? cb[ge[i] & 0xFFFFu] : 0.0;
+            int tc = -1;
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < kGent; ++i) {
+                if (ge[i] == kGentNone) break;
+                const int tt = (int)(ge[i] >> 16);
+                if (tt != tc) {
+                    if (tc >= 0) Gam[tc] += acc;
+                    tc = tt;
+                    acc = 0.0;
+                }
+                acc += v[i];
+            }
+            if (tc >= 0) Gam[tc] += acc;
         }
+        if (k + 1 < S.nchunk) fetch_gather(k + 1);
         __syncthreads();
+    }
+    // the s1 sums' derivative-table values, loaded now and used after Y and
+    // Zc: s1[e][q] = sum_m G_q[e][m] 2^-E[m] Y[m][e] in nf segments of m per
+    // (e, q)
+    const int nf = max(1, min(8, kBlock / (4 * n)));
+    const double *phig = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
+    const bool s1t = tid < nf * 4 * n;
+    const int pr = tid / nf, g1 = tid - pr * nf, e1 = pr >> 2, q1 = pr & 3;
+    const double *Gq1 = phig + (size_t)e1 * 5 * M + (size_t)(1 + q1) * M;
+    double gpre[kS1Pre];
+#pragma unroll
+    for (int u = 0; u < kS1Pre; ++u) {
+        const int m = g1 + u * nf;
+        gpre[u] = (s1t && m < M) ? Gq1[m] : 0.0;
     }
     // Y = Gamma^T X on the matrix cores (Y[m][e], row stride n): tiles of 16
     // orbitals m, K = the n slots c in steps of 4
@@ -1296,52 +1320,61 @@ __global__ void __launch_bounds__(kBlock, 4) k_deriv(KernelArgs a) {
         Zc[idx] = s;
     }
     __syncthreads();
-    // s1[e][q] = sum_m G_q[e][m] 2^-E[m] Y[m][e]: nf segments of m per (e, q),
-    // eight loads in flight per step
-    const int nf = max(1, min(8, 256 / (4 * n)));
-    const double *phig = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
-    if (tid < nf * 4 * n) {
-        const int pr = tid / nf, g = tid - pr * nf;
-        const int e = pr >> 2, q = pr & 3;
-        const double *Gq = phig + (size_t)e * 5 * M + (size_t)(1 + q) * M;
+    // the output threads' loads, issued before the s1 sums: the orbital
+    // derivatives at the reference's occupied orbitals (occupied columns
+    // clamped to n), the reference term and the psi partial sums (to LDS)
+    const int eo = tid >> 2, qo = tid & 3;
+    double go[kMaxN];
+    double g0 = 0.0;
+    if (tid < 4 * n) {
+        const double *Gq = phig + (size_t)eo * 5 * M + (size_t)(1 + qo) * M;
+#pragma unroll
+        for (int c = 0; c < kMaxN; ++c) go[c] = Gq[occ0[c < n ? c : n - 1]];
+        g0 = a.wk.g0[((size_t)w * N + S.e0 + eo) * 4 + qo];
+    }
+    double *psiP = scr + kBlock;  // [2][kPsiParts]
+    if (tid < 2 * kPsiParts) psiP[tid] = a.wk.psi64[(size_t)w * 2 * kPsiParts + tid];
+    if (s1t) {
         double s = 0.0;
-        int m = g;
+#pragma unroll
+        for (int u = 0; u < kS1Pre; ++u) {
+            const int m = g1 + u * nf;
+            if (m < M) s += (gpre[u] * pow2(-Ex[m])) * Y[m * n + e1];
+        }
+        int m = g1 + kS1Pre * nf;
         for (; m + 7 * nf < M; m += 8 * nf) {
             double gv[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) gv[u] = Gq[m + u * nf];
+            for (int u = 0; u < 8; ++u) gv[u] = Gq1[m + u * nf];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int mm = m + u * nf;
-                s += (gv[u] * pow2(-Ex[mm])) * Y[mm * n + e];
+                s += (gv[u] * pow2(-Ex[mm])) * Y[mm * n + e1];
             }
         }
-        for (; m < M; m += nf) s += (Gq[m] * pow2(-Ex[m])) * Y[m * n + e];
+        for (; m < M; m += nf) s += (Gq1[m] * pow2(-Ex[m])) * Y[m * n + e1];
         scr[tid] = s;
     }
     __syncthreads();
     if (tid < 4 * n) {
-        const int e = tid >> 2, q = tid & 3;
-        const double *Gq = phig + (size_t)e * 5 * M + (size_t)(1 + q) * M;
-        const size_t o = ((size_t)w * N + S.e0 + e) * 4 + q;
-        // the phase's loads issued together (occupied columns clamped to n)
-        double go[kMaxN];
-#pragma unroll
-        for (int c = 0; c < kMaxN; ++c) go[c] = Gq[occ0[c < n ? c : n - 1]];
-        const double g0 = a.wk.g0[o];
+        const size_t o = ((size_t)w * N + S.e0 + eo) * 4 + qo;
         // the derivative of Psi for this spin's electrons is the numerator
         // g0 psi_sigma + (s1 - s2): psi_sigma is formed from the same ratios
         // and weights as the aggregate, so a rounding of the weights cannot
         // be amplified by a large g0; divided by psi_up, the psi that gives
         // ln|Psi|, so that the returned ratio times the returned Psi is that
-        // numerator
-        const double psi = psi_value(a, w, 0);
-        const double gr = sp ? g0 * (psi_value(a, w, 1) / psi) : g0;
+        // numerator.  The partial sums are added in the order of psi_value.
+        const int np = a.psi_nparts;
+        double psi = 0.0, psi_s = 0.0;
+        for (int k = 0; k < np; ++k) psi += psiP[k];
+        if (sp)
+            for (int k = 0; k < np; ++k) psi_s += psiP[kPsiParts + k];
+        const double gr = sp ? g0 * (psi_s / psi) : g0;
         double s1 = 0.0, s2 = 0.0;
         for (int g = 0; g < nf; ++g) s1 += scr[tid * nf + g];
 #pragma unroll
         for (int c = 0; c < kMaxN; ++c)
-            if (c < n) s2 += (go[c] * pow2(-Ex[occ0[c]])) * Zc[c * n + e];
+            if (c < n) s2 += (go[c] * pow2(-Ex[occ0[c]])) * Zc[c * n + eo];
         a.gl_out[o] = gr + (s1 - s2) / psi;
     }
 }
