@@ -130,6 +130,23 @@ def test_forced_fallback_path():
     assert ep.max() <= MIXED_TOL and eg.max() <= MIXED_TOL
 
 
+def test_forced_fallback_more_items_than_blocks():
+    """160 walkers, every (walker, spin) through the fallback: 320 listed
+    pairs, more (pair, slice) items than the fixed grids of the fallback
+    kernels have blocks, so that blocks take several items in turn."""
+    log("[parity] forced fallback config 2, 320 listed pairs")
+    wl = workload(2)
+    ev = evaluator(wl)
+    ev.set_fallback_threshold(1e-300)
+    W = 160
+    for prec, tol in ((mdet.MDET_FP64, FP64_TOL), (mdet.MDET_MIXED, MIXED_TOL)):
+        sign, logabs, gl, ws = gpu_eval(ev, wl.R[:W], precision=prec)
+        assert np.all(ws == mdet.W_FALLBACK)
+        ep, eg = scaled_errors(_sub(oracle_ref(2), W), sign, logabs, gl)
+        summary(f"c2 forced fallback W={W} prec{prec}", ep, eg)
+        assert ep.max() <= tol and eg.max() <= tol
+
+
 def test_node_origin_and_tiny_config():
     log("[parity] nodes and origin, config 1")
     wl = workload(1)
