@@ -1460,20 +1460,116 @@ __device__ __forceinline__ void lu_regs(double (&a)[K][K], int (&perm)[K], doubl
     ex = k;
 }
 
-// occupied orbital of slot c for determinant D (reference with holes replaced)
-// (H: the holes and particles of a determinant of degree above kFastDegree,
-// null otherwise)
-__device__ __forceinline__ int slot_orbital(const DetDesc &D, const DetDescHi *H, const int *occ0,
-                                            int c) {
-    int o = occ0[c];
-    if (H) {
-        for (int t = 0; t < D.s; ++t)
-            if (H->h[t] == c) o = H->p[t];
-    } else {
-        for (int t = 0; t < D.s; ++t)
-            if (D.h[t] == c) o = D.p[t];
+// In-place Gauss-Jordan inversion of a[K][K] with column pivoting: step j
+// takes as pivot the largest |entry| of row j among columns j..K-1 (the
+// lowest column on ties) and exchanges that column with column j, occ[]
+// along with it.  On return a = (A Q)^-1 for the column permutation Q, so
+// that row c of the result belongs to orbital occ[c]; det A = mant * 2^ex
+// (mant = 0 on a zero pivot, a then undefined).  Every other row is reduced
+// by the multiplier a[i][j] / pivot times the unscaled pivot row, as in the
+// LU, so equal rows still give an exactly zero pivot.
+// one pivot step j of gj_inverse_cols (a template, so that every register
+// index is static); returns false on a zero pivot
+template <int K, int J>
+__device__ __forceinline__ bool gj_step(double (&a)[K][K], int (&occ)[K], double &m, int &k) {
+    int p = J;
+    double best = fabs(a[J][J]);
+#pragma unroll
+    for (int c = J + 1; c < K; ++c)
+        if (fabs(a[J][c]) > best) {
+            best = fabs(a[J][c]);
+            p = c;
+        }
+    if (!(best > 0.0)) return false;
+    // column exchange by selects (no branches: the matrix stays in registers)
+#pragma unroll
+    for (int c = J + 1; c < K; ++c) {
+        const bool sw = c == p;
+#pragma unroll
+        for (int r = 0; r < K; ++r) {
+            const double x = a[r][c], y = a[r][J];
+            a[r][c] = sw ? y : x;
+            a[r][J] = sw ? x : y;
+        }
+        const int x = occ[c], y = occ[J];
+        occ[c] = sw ? y : x;
+        occ[J] = sw ? x : y;
     }
-    return o;
+    if (p != J) m = -m;
+    const double piv = a[J][J];
+    m *= piv;
+    int kk;
+    m = frexp(m, &kk);
+    k += kk;
+    const double rinv = 1.0 / piv;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+        if (i == J) continue;
+        const double l = div_by(a[i][J], piv, rinv);
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+            if (c != J) a[i][c] -= l * a[J][c];
+        a[i][J] = -l;
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+        if (c != J) a[J][c] *= rinv;
+    a[J][J] = rinv;
+    if constexpr (J + 1 < K) return gj_step<K, J + 1>(a, occ, m, k);
+    else return true;
+}
+
+// In-place Gauss-Jordan inversion of a[K][K] with column pivoting: step j
+// takes as pivot the largest |entry| of row j among columns j..K-1 (the
+// lowest column on ties) and exchanges that column with column j, occ[]
+// along with it.  On return a = (A Q)^-1 for the column permutation Q, so
+// that row c of the result belongs to orbital occ[c]; det A = mant * 2^ex
+// (mant = 0 on a zero pivot, a then undefined).  Every other row is reduced
+// by the multiplier a[i][j] / pivot times the unscaled pivot row, as in the
+// LU, so equal rows still give an exactly zero pivot.
+template <int K>
+__device__ __forceinline__ void gj_inverse_cols(double (&a)[K][K], int (&occ)[K], double &mant,
+                                                int &ex) {
+    double m = 1.0;
+    int k = 0;
+    if (gj_step<K, 0>(a, occ, m, k)) {
+        mant = m;
+        ex = k;
+    } else {
+        mant = 0.0;
+        ex = 0;
+    }
+}
+
+// occupied orbitals occ[c] of the slots c < n of determinant D (the
+// reference's occ0 with the holes replaced by the particles), 0 beyond n;
+// H: the holes and particles of a determinant of degree above kFastDegree,
+// null otherwise.  Every register index is static (the holes and particles
+// are unpacked from whole words), so nothing goes through scratch memory.
+template <int K>
+__device__ __forceinline__ void det_orbitals(const DetDesc &D, const DetDescHi *H, const int *occ0,
+                                             int n, int (&occ)[K]) {
+#pragma unroll
+    for (int c = 0; c < K; ++c) occ[c] = (c < n) ? occ0[c] : 0;
+    auto put = [&](int h, int p) {
+#pragma unroll
+        for (int c = 0; c < K; ++c) occ[c] = (c == h) ? p : occ[c];
+    };
+    if (H) {
+        const uint2 hv = *reinterpret_cast<const uint2 *>(H->h);
+        const uint2 p0 = *reinterpret_cast<const uint2 *>(H->p);
+        const uint2 p1 = *reinterpret_cast<const uint2 *>(H->p + 4);
+        const uint32_t pw[4] = {p0.x, p0.y, p1.x, p1.y};
+#pragma unroll
+        for (int t = 0; t < MDET_MAX_DEGREE; ++t)
+            if (t < D.s)
+                put((int)(((t < 4 ? hv.x : hv.y) >> (8 * (t & 3))) & 0xFFu),
+                    (int)((pw[t >> 1] >> (16 * (t & 1))) & 0xFFFFu));
+    } else {
+#pragma unroll
+        for (int t = 0; t < kFastDegree; ++t)
+            if (t < D.s) put((int)D.h[t], (int)D.p[t]);
+    }
 }
 
 template <typename T>
@@ -1491,9 +1587,9 @@ __device__ __forceinline__ int direct_matrix(const DetDesc &D, const DetDescHi *
                                              const int *occ0, const double *P0, const int *Ex,
                                              int M, int n, double (&A)[K][K], int (&occ)[K]) {
     int sx = 0;
+    det_orbitals<K>(D, H, occ0, n, occ);
 #pragma unroll
     for (int c = 0; c < K; ++c) {
-        occ[c] = (c < n) ? slot_orbital(D, H, occ0, c) : 0;
         if (c < n) sx += Ex[occ[c]];
 #pragma unroll
         for (int e = 0; e < K; ++e) {
@@ -1539,118 +1635,158 @@ __device__ __forceinline__ int direct_ratio_item(const KernelArgs &a, int sp, in
     return kmax;
 }
 
+// per-thread inputs of one determinant of the derivative pass: descriptor,
+// exponent of its ratio (INT_MIN if singular) and its weight u or v
+struct DirectDet {
+    DetDesc D;
+    int rexp;
+    double wt;
+};
+
+__device__ __forceinline__ DirectDet direct_det_load(const KernelArgs &a, const SpinDev &S, int sp,
+                                                     int w, int d) {
+    DirectDet X;
+    X.D = S.desc[d];
+    const size_t o = rv_index(a, sp, d, w);
+    X.rexp = a.wk.Rexp[o];
+    X.wt = a.precision == MDET_MIXED ? (double)a.wk.uv32[o] : a.wk.uv64[o];
+    return X;
+}
+
 // one work item of the derivative pass: adds, per electron e and component
-// q, the wave sums of  w_d R_d grad~_e D_d / D_d  (row-replacement form with
-// the columns of S_d^-1) to red[wave][e*4 + q]
+// q, the wave sums of  w_d D_d grad~_e D_d / D_d  (row-replacement form with
+// column e of S_d^-1) to red[wave][e*4 + q].  P0 holds the unscaled orbital
+// values, Gs (if not null) the unscaled derivatives, else Gg points at the
+// orbital array; columns are scaled by 2^-Ex at the matrix and the rows of
+// the inverse scaled back.  `first` is the thread's determinant d0 + tid,
+// loaded before the staging.
 template <int K>
-__device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, int w, const SpinDev &S,
-                                  const int *occ0, const double *P0, const double *Gs,
-                                  const double *Gg, const int *Ex, int d0, int d1,
-                                  double *red, double *wr) {
+__device__ __forceinline__ void direct_deriv_item(const KernelArgs &a, int sp, int w,
+                                                  const SpinDev &S, const int *occ0,
+                                                  const double *P0, const double *Gs,
+                                                  const double *Gg, const int *Ex, int d0, int d1,
+                                                  const DirectDet &first, double *red, double *wr) {
     const int M = a.M, n = S.n;
     const int dmax = a.max_degree ? (int)a.max_degree[w] : 1 << 20;
     const int Kx = a.wk.K[(size_t)w * 2 + sp];
-    const bool mixed = a.precision == MDET_MIXED;
+    const int Ulo = S.deg_end[kFastDegree];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int base = d0; base < d1; base += kDirectBlock) {
         // every lane takes part in the wave sums; lanes without a valid
         // determinant contribute zeros
         const int d = base + (int)threadIdx.x;
         const bool in = d < d1;
-        const DetDesc D = S.desc[in ? d : d0];
-        const int Ulo = S.deg_end[kFastDegree];
-        const DetDescHi *H = (in ? d : d0) >= Ulo ? S.desc_hi + ((in ? d : d0) - Ulo) : nullptr;
-        const size_t o = rv_index(a, sp, in ? d : d0, w);
-        const int rexp = a.wk.Rexp[o];
-        bool valid = in && D.s <= dmax && rexp != INT_MIN;
+        const int dd = in ? d : d0;
+        const DirectDet X = base == d0 ? first : direct_det_load(a, S, sp, w, dd);
+        const DetDescHi *H = dd >= Ulo ? S.desc_hi + (dd - Ulo) : nullptr;
         double A[K][K];
-        int occ[K], perm[K];
-        direct_matrix<K>(D, H, occ0, P0, Ex, M, n, A, occ);
+        int occ[K];
+        int sx = 0;
+        det_orbitals<K>(X.D, H, occ0, n, occ);
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+            const double sc = pow2(-Ex[occ[c]]);
+            if (c < n) sx += Ex[occ[c]];
+#pragma unroll
+            for (int e = 0; e < K; ++e) {
+                const double v = P0[min(e, n - 1) * M + occ[c]] * sc;
+                A[e][c] = (c < n) ? ((e < n) ? v : 0.0) : ((e == c) ? 1.0 : 0.0);
+            }
+        }
         double mant;
         int ex;
-        lu_regs<K, true>(A, perm, mant, ex);
-        valid = valid && mant != 0.0;
-        const double wt = mixed ? (double)a.wk.uv32[o] : a.wk.uv64[o];
-        const double coef = valid ? wt * ldexp((double)D.eps * mant, rexp - Kx) : 0.0;
+        gj_inverse_cols<K>(A, occ, mant, ex);
+        const bool valid = in && X.D.s <= dmax && X.rexp != INT_MIN && mant != 0.0;
+        const double coef =
+            valid ? X.wt * ldexp((double)X.D.eps * mant, ex + sx - Kx) : 0.0;
+        // row c of the inverse belongs to orbital occ[c]: scale it back
 #pragma unroll
-        for (int i = 0; i < K; ++i) A[i][i] = 1.0 / A[i][i];  // U's diagonal, inverted
-        for (int e0 = 0; e0 < n; e0 += kEHalf) {
-        const int e1 = min(n, e0 + kEHalf);
-#pragma unroll 1
-        for (int e = e0; e < e1; ++e) {
-            // column e of S_d^-1
-            double x[K];
+        for (int c = 0; c < K; ++c) {
+            const double sc = pow2(-Ex[occ[c]]);
 #pragma unroll
-            for (int i = 0; i < K; ++i) x[i] = (perm[i] == e) ? 1.0 : 0.0;
+            for (int e = 0; e < K; ++e) A[c][e] *= sc;
+        }
 #pragma unroll
-            for (int i = 0; i < K; ++i)
+        for (int g = 0; g < (K + kEHalf - 1) / kEHalf; ++g) {
 #pragma unroll
-                for (int j = 0; j < i; ++j) x[i] -= A[i][j] * x[j];
+            for (int i = 0; i < kEHalf; ++i) {
+                const int e = g * kEHalf + i;
+                if (e < K && e < n) {
 #pragma unroll
-            for (int i = K - 1; i >= 0; --i) {
+                    for (int q = 0; q < 4; ++q) {
+                        const double *G = Gs ? Gs + (size_t)(q * n + e) * M
+                                             : Gg + (size_t)e * 5 * M + (size_t)(1 + q) * M;
+                        double s = 0.0;
 #pragma unroll
-                for (int j = i + 1; j < K; ++j) x[i] -= A[i][j] * x[j];
-                x[i] *= A[i][i];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                double s = 0.0;
-                if (Gs) {
-                    const double *G = Gs + (size_t)(q * n + e) * M;
-#pragma unroll
-                    for (int c = 0; c < K; ++c)
-                        if (c < n) s += x[c] * G[occ[c]];
-                } else {
-                    const double *G = Gg + (size_t)e * 5 * M + (size_t)(1 + q) * M;
-#pragma unroll
-                    for (int c = 0; c < K; ++c)
-                        if (c < n) s += x[c] * (G[occ[c]] * pow2(-Ex[occ[c]]));
+                        for (int c = 0; c < K; ++c)
+                            if (c < n) s += A[c][e < K ? e : 0] * G[occ[c]];
+                        wr[lane * kWredLd + i * 4 + q] = valid ? coef * s : 0.0;
+                    }
                 }
-                wr[lane * kWredLd + (e - e0) * 4 + q] = valid ? coef * s : 0.0;
             }
-        }
-        // the wave's sums of this group of electrons: lane t adds column t over the lanes
-        wave_lds_sync();
-        if (lane < (e1 - e0) * 4) {
-            double t = 0.0;
-            for (int l = 0; l < 64; ++l) t += wr[l * kWredLd + lane];
-            red[wave * 4 * K + e0 * 4 + lane] += t;
-        }
-        wave_lds_sync();
+            // the wave's sums of this group of electrons: lane t adds column t
+            // over the lanes (four interleaved partial sums)
+            const int e0 = g * kEHalf, ne = min(n, e0 + kEHalf) - e0;
+            wave_lds_sync();
+            if (lane < ne * 4) {
+                double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+                for (int l = 0; l < 64; l += 4) {
+                    t0 += wr[l * kWredLd + lane];
+                    t1 += wr[(l + 1) * kWredLd + lane];
+                    t2 += wr[(l + 2) * kWredLd + lane];
+                    t3 += wr[(l + 3) * kWredLd + lane];
+                }
+                red[wave * 4 * K + e0 * 4 + lane] += (t0 + t1) + (t2 + t3);
+            }
+            wave_lds_sync();
         }
     }
 }
 
-// stage the scaled orbital values (and, if G is not null, the derivatives) of
-// electrons e0 .. e0+n-1 of walker w: dst[(q*n + e)*M + m] = phi_q * 2^-E[m]
-__device__ void stage_orbitals(const KernelArgs &a, int w, int e0, int n, const int *Ex,
-                               double *P0, double *G) {
+// stage the orbital values (and, if G is not null, the derivatives) of
+// electrons e0 .. e0+n-1 of walker w: P0[e*M + m] = phi * 2^-E[m] (SCALE) or
+// phi, and G[((q-1)*n + e)*M + m] = the derivative plane q = 1..4 (unscaled).
+// KU loads are in flight per thread before the stores; a thread walks its
+// elements with a running (electron, offset) pair instead of divisions, and
+// past the end it loads element 0 again rather than skipping the load, so
+// that the loads are issued together.
+template <bool SCALE, int KU>
+__device__ __forceinline__ void stage_orbitals(const KernelArgs &a, int w, int e0, int n,
+                                               const int *Ex, double *P0, double *G) {
     const int M = a.M;
     const double *phig = a.wk.phi + ((size_t)w * a.N + e0) * 5 * M;
-    // source index j over the planes taken: [e][q][m] with q < nq (contiguous
-    // when all five are taken); eight loads in flight per thread before the stores
-    const int nq = G ? 5 : 1;
-    const int tot = n * nq * M;
-    constexpr int kU = 8;
-    for (int base = threadIdx.x; base < tot; base += kU * blockDim.x) {
-        double v[kU];
+    // element (e, r) of the planes taken: plane q = r / M < nq, orbital r % M
+    const int nq = G ? 5 : 1, nqM = nq * M;
+    const int step = (int)blockDim.x;
+    int e = 0, r = (int)threadIdx.x;
+    while (r >= nqM) {
+        r -= nqM;
+        ++e;
+    }
+    while (e < n) {
+        double v[KU];
+        int ev[KU], rv[KU];
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int j = base + u * (int)blockDim.x;
-            v[u] = 0.0;
-            if (j < tot) {
-                const int e = j / (nq * M), r = j - e * nq * M;
-                v[u] = phig[(size_t)e * 5 * M + r];
+        for (int u = 0; u < KU; ++u) {
+            ev[u] = e;
+            rv[u] = r;
+            v[u] = phig[e < n ? (size_t)e * 5 * M + r : 0];
+            r += step;
+            while (r >= nqM) {
+                r -= nqM;
+                ++e;
             }
         }
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-            const int j = base + u * (int)blockDim.x;
-            if (j < tot) {
-                const int e = j / (nq * M), r = j - e * nq * M, q = r / M, m = r - q * M;
-                const double x = v[u] * pow2(-Ex[m]);
-                if (q == 0) P0[e * M + m] = x;
-                else G[((q - 1) * n + e) * M + m] = x;
+        for (int u = 0; u < KU; ++u) {
+            if (ev[u] < n) {
+                const int rr = rv[u];
+                const int q = nq == 1 ? 0
+                                      : (rr >= M) + (rr >= 2 * M) + (rr >= 3 * M) + (rr >= 4 * M);
+                const int m = rr - q * M;
+                const double x = SCALE ? v[u] * pow2(-Ex[m]) : v[u];
+                if (q == 0) P0[ev[u] * M + m] = x;
+                else G[((q - 1) * n + ev[u]) * M + m] = x;
             }
         }
     }
@@ -1702,7 +1838,7 @@ __global__ void __launch_bounds__(kDirectBlock, 2) k_direct_ratios_t(KernelArgs 
         for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[(size_t)ws * M + m];
         for (int c = tid; c < n; c += kDirectBlock) occ0[c] = S.occ0[c];
         __syncthreads();
-        stage_orbitals(a, w, S.e0, n, Ex, P0, nullptr);
+        stage_orbitals<true, 8>(a, w, S.e0, n, Ex, P0, nullptr);
         __syncthreads();
         const int d0 = (int)((int64_t)S.U * part / split);
         const int d1 = (int)((int64_t)S.U * (part + 1) / split);
@@ -1750,12 +1886,12 @@ __global__ void __launch_bounds__(kBlock) k_direct_scale(KernelArgs a) {
 
 // pass 3 (after the sparse combination): derivative partial sums per item
 template <int NT>
-__global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a) {
+__global__ void __launch_bounds__(kDirectBlock, 2) k_direct_deriv_t(KernelArgs a) {
     const int M = a.M, N = a.N, tid = threadIdx.x, split = a.direct_split;
     const bool stage_g = a.direct_stage_grad != 0;
     extern __shared__ double lds[];
-    double *P0 = lds;                                  // [NT][M] scaled values
-    double *G = stage_g ? P0 + NT * M : nullptr;       // [4][NT][M] scaled derivatives
+    double *P0 = lds;                                  // [NT][M] unscaled values
+    double *G = stage_g ? P0 + NT * M : nullptr;       // [4][NT][M] unscaled derivatives
     double *red = P0 + (stage_g ? 5 : 1) * NT * M;     // [kDirectBlock / 64][NT * 4]
     double *wred = red + (kDirectBlock / 64) * NT * 4;  // [kDirectBlock / 64][64][kWredLd]
     int *Ex = (int *)(wred + (kDirectBlock / 64) * 64 * kWredLd);  // [M]
@@ -1767,24 +1903,31 @@ __global__ void __launch_bounds__(kDirectBlock) k_direct_deriv_t(KernelArgs a) {
         const int w = ws >> 1, sp = ws & 1;
         const SpinDev &S = a.sp[sp];
         const int n = S.n;
-        __syncthreads();  // the previous item is done with the LDS
-        for (int m = tid; m < M; m += kDirectBlock) Ex[m] = a.wk.E[(size_t)ws * M + m];
-        for (int c = tid; c < n; c += kDirectBlock) occ0[c] = S.occ0[c];
-        for (int i = tid; i < (kDirectBlock / 64) * NT * 4; i += kDirectBlock) red[i] = 0.0;
-        __syncthreads();
-        stage_orbitals(a, w, S.e0, n, Ex, P0, G);
-        __syncthreads();
-        const double *Gg = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
         const int d0 = (int)((int64_t)S.U * part / split);
         const int d1 = (int)((int64_t)S.U * (part + 1) / split);
+        __syncthreads();  // the previous item is done with the LDS
+        // the thread's first determinant and the column exponents (at most
+        // MDET_MAX_MO = 2 kDirectBlock of them) are loaded while the block
+        // stages the orbitals
+        const DirectDet first = direct_det_load(a, S, sp, w, d0 + tid < d1 ? d0 + tid : 0);
+        static_assert(MDET_MAX_MO <= 2 * kDirectBlock, "column exponents: two per thread");
+        const int ex0 = a.wk.E[(size_t)ws * M + min(tid, M - 1)];
+        const int ex1 = a.wk.E[(size_t)ws * M + min(tid + kDirectBlock, M - 1)];
+        for (int c = tid; c < n; c += kDirectBlock) occ0[c] = S.occ0[c];
+        for (int i = tid; i < (kDirectBlock / 64) * NT * 4; i += kDirectBlock) red[i] = 0.0;
+        stage_orbitals<false, 24>(a, w, S.e0, n, nullptr, P0, G);
+        if (tid < M) Ex[tid] = ex0;
+        if (tid + kDirectBlock < M) Ex[tid + kDirectBlock] = ex1;
+        __syncthreads();
+        const double *Gg = a.wk.phi + ((size_t)w * N + S.e0) * 5 * M;
         int K;
         if (NT > 1 && n == NT - 1) {
             K = NT > 1 ? NT - 1 : 1;
             direct_deriv_item<(NT > 1 ? NT - 1 : 1)>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1,
-                                                      red, wred + (tid >> 6) * 64 * kWredLd);
+                                                      first, red, wred + (tid >> 6) * 64 * kWredLd);
         } else {
             K = NT;  // n <= NT
-            direct_deriv_item<NT>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1, red,
+            direct_deriv_item<NT>(a, sp, w, S, occ0, P0, G, Gg, Ex, d0, d1, first, red,
                                   wred + (tid >> 6) * 64 * kWredLd);
         }
         __syncthreads();
