@@ -443,12 +443,12 @@ WORKLOAD_LABEL = {
 }
 
 
-def measure_config(cid, steps, warmup, tune, n_sample, precisions=(1, 0)):
+def measure_config(cid, steps, warmup, tune, n_sample, precisions=(1, 0), raw_order=False):
     """Both precisions of one workload: rates (eager and graph replay), every
     kernel's time and roofline entry, and the errors of a timed step's walkers
     against the oracle."""
     from gen.workloads import make_config, walker_pool
-    wl = make_config(cid)
+    wl = make_config(cid, raw_orbital_order=raw_order)
     pool = walker_pool(wl, 8)
     sh = Shape(wl)
     W = wl.n_walk
@@ -496,6 +496,9 @@ def main():
                     help="skip the other workloads' rows")
     ap.add_argument("--sample", type=int, default=64,
                     help="walkers of a timed step checked against the oracle")
+    ap.add_argument("--raw-orbital-order", action="store_true",
+                    help="keep the orbitals in the order drawn (near-singular reference at "
+                         "most walkers: the conditioning fallback's stress case); headline only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB buffer (traffic-counter calibration) and exit")
     args = ap.parse_args()
@@ -508,8 +511,10 @@ def main():
         return
     prec = 1 if args.precision == "mixed" else 0
     pname = "mixed" if prec else "fp64"
+    if args.raw_orbital_order:
+        args.headline_only, args.no_chain = True, True
     wl, res = measure_config(args.config, args.steps, args.warmup, not args.no_tune, args.sample,
-                             precisions=(prec, 1 - prec))
+                             precisions=(prec, 1 - prec), raw_order=args.raw_orbital_order)
     r = res[pname]
     W = wl.n_walk
     roof = dict(r["kernels"][r["dominant_kernel"]])
@@ -526,7 +531,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64+f32" if prec == 1 else "f64",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_LABEL[args.config], "precision": pname,
+        "config": {"workload": WORKLOAD_LABEL[args.config] +
+                   (" (orbitals in drawn order)" if args.raw_orbital_order else ""),
+                   "precision": pname,
                    "walker_batch": W, "launch_config": r["launch_config"],
                    "fallback_fraction": r["fallback_fraction"]},
         "fp64_value": res["fp64"]["value"],

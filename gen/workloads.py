@@ -103,13 +103,17 @@ def encode(occ_lists, n_int: int) -> np.ndarray:
     return out
 
 
-def _orbitals(rng, n_mo, n_prim):
+def _orbitals(rng, n_mo, n_prim, relabel=True):
     mono = rng.integers(0, len(MONOMIALS), size=(n_mo, n_prim))
     pow_abc = np.array(MONOMIALS, dtype=np.int32)[mono]
     alpha = np.exp(rng.uniform(math.log(0.1), math.log(50.0), size=(n_mo, n_prim)))
     coef = rng.standard_normal((n_mo, n_prim))
     # label the orbitals diffuse-first (ascending smallest exponent), so the
-    # reference determinant (orbitals 0..n-1) holds the most diffuse ones
+    # reference determinant (orbitals 0..n-1) holds the most diffuse ones;
+    # relabel=False keeps the order of the draw (a near-singular reference
+    # at most walkers: the stress case of the conditioning fallback)
+    if not relabel:
+        return pow_abc.astype(np.int32), alpha, coef
     order = np.argsort(alpha.min(axis=1), kind="stable")
     return pow_abc[order].astype(np.int32), alpha[order], coef[order]
 
@@ -153,17 +157,20 @@ def _pairs(rng, n_det, nu, nd):
     return flat // nd, flat % nd
 
 
-def make_config(cid: int, seed: Optional[int] = None, n_walk: Optional[int] = None) -> Workload:
-    """Build benchmark workload ``cid`` (1..5) from SeedSequence(1000+cid)."""
+def make_config(cid: int, seed: Optional[int] = None, n_walk: Optional[int] = None,
+                raw_orbital_order: bool = False) -> Workload:
+    """Build benchmark workload ``cid`` (1..5) from SeedSequence(1000+cid);
+    ``raw_orbital_order`` keeps the orbitals in the order drawn."""
     spec = dict(CONFIGS[cid])
     if "base" in spec:
-        base = make_config(spec["base"], seed=seed, n_walk=n_walk or spec["n_walk"])
+        base = make_config(spec["base"], seed=seed, n_walk=n_walk or spec["n_walk"],
+                           raw_orbital_order=raw_orbital_order)
         base.name = spec["name"]
         return base
     ss = np.random.SeedSequence(1000 + cid if seed is None else seed)
     s_orb, s_up, s_dn, s_pair, s_coef, s_walk, s_deg = (np.random.default_rng(s) for s in ss.spawn(7))
     n_up, n_dn, n_mo, n_prim = spec["n_up"], spec["n_dn"], spec["n_mo"], spec["n_prim"]
-    pow_abc, alpha, coef = _orbitals(s_orb, n_mo, n_prim)
+    pow_abc, alpha, coef = _orbitals(s_orb, n_mo, n_prim, relabel=not raw_orbital_order)
     n_int = (n_mo + 63) // 64
     ups = _unique_dets(s_up, n_up, n_mo, spec["n_uniq"], spec["degrees"])
     dns = _unique_dets(s_dn, n_dn, n_mo, spec["n_uniq"], spec["degrees"])

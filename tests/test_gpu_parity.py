@@ -147,6 +147,24 @@ def test_forced_fallback_more_items_than_blocks():
         assert ep.max() <= tol and eg.max() <= tol
 
 
+def test_drawn_orbital_order_fallback_heavy():
+    """Orbitals in the order drawn instead of diffuse-first: the reference
+    determinant is near-singular at most walkers, so most (walker, spin)
+    pairs take the conditioning fallback.  64 walkers of config 3, both
+    precisions, against the oracle at the usual bars."""
+    log("[parity] config 3, orbitals in drawn order, 64 walkers")
+    wl = make_config(3, n_walk=64, raw_orbital_order=True)
+    ev = evaluator(wl)
+    ref = oracle.evaluate(wl, wl.R, n_threads=16)
+    for prec, tol in ((mdet.MDET_FP64, FP64_TOL), (mdet.MDET_MIXED, MIXED_TOL)):
+        sign, logabs, gl, ws = gpu_eval(ev, wl.R, precision=prec)
+        ep, eg = scaled_errors(ref, sign, logabs, gl)
+        summary(f"c3 drawn order W=64 prec{prec}", ep, eg, ws)
+        if prec == mdet.MDET_FP64:
+            assert np.mean(ws == mdet.W_FALLBACK) > 0.3
+        assert ep.max() <= tol and eg.max() <= tol
+
+
 def test_node_origin_and_tiny_config():
     log("[parity] nodes and origin, config 1")
     wl = workload(1)
