@@ -13,6 +13,8 @@ shares no code with the GPU path.
 * ``preprocess.py``: the paper's determinant ordering and sparse indexing
   (Sec. 2.1), written independently of the library's C++ version.
 * ``brute.py``: brute-force references for tiny inputs.
+* ``extended.py``: the same sums in extended precision for a few walkers,
+  to tell which of two disagreeing FP64 evaluations is the more accurate.
 * ``mlp.py``, ``vmc.py``: FP64 references for the learned proposal and the
   Metropolis step.
 """
