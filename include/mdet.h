@@ -231,12 +231,12 @@ mdet_status mdet_eval_walkers_noalloc(mdet_ctx *ctx, int64_t n_walk, const doubl
  * scaled derivative error up to 5e-11 below 3e4, 1e-8 to 3e-7 between 3e4
  * and 1e7, 1e-4 above), so each precision's threshold follows its error
  * bound (1e-10 in FP64, 1e-5 in mixed precision).  The defaults are
- * calibrated on that workload's orbitals; kappa_1 bounds the reference's
- * conditioning but not that of the minors, so inputs whose minors are worse
- * at the same kappa_1 need a lower threshold (the same workload with its
- * orbitals in drawn order: at 3e4, 1.8 % of the walkers above 1e-10 in
- * FP64, the largest 1.6e-8; at 1e3, 99.6 % of the walkers fall back and one
- * of the 180 worst stays above it, at 1.04e-10).
+ * calibrated on that workload's orbitals; on other inputs the same kappa_1
+ * can leave a larger derivative error (the same workload with its orbitals
+ * in drawn order, FP64 at 3e4: Psi within 1.2e-11 everywhere, but the
+ * derivatives of 1.8 % of the walkers above 1e-10, the largest 1.6e-8; at
+ * 1e3, 99.6 % of the walkers fall back and one of the 180 worst stays
+ * above it, at 1.04e-10), and such inputs need a lower threshold.
  *  precision  MDET_FP64, MDET_MIXED, or -1 for both.
  *  kappa_max  > 0; defaults MDET_KAPPA_FP64_DEFAULT and MDET_KAPPA_MIXED_DEFAULT.
  * Takes effect at the next evaluation; captured steps (mdet_eval_graph) are
