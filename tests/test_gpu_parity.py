@@ -155,9 +155,10 @@ def test_drawn_orbital_order_fallback_heavy():
     mixed precision at its default threshold, at the usual bars.  FP64 at
     its default threshold (kappa_1 <= 3e4 keeps the table method) is held
     to a looser bound: on this input distribution the reference's kappa_1
-    does not bound the error of the minors, and over 8192 such walkers 1.8 %
-    exceed 1e-10 (the largest 1.6e-8; the oracle agrees with an
-    extended-precision evaluation to 1e-12 there)."""
+    does not bound the error of the table method's derivative sums, and over
+    8192 such walkers the derivatives of 1.8 % exceed 1e-10 (the largest
+    1.6e-8, psi within 1.2e-11; the oracle agrees with an extended-precision
+    evaluation to 1e-12 there)."""
     log("[parity] config 3, orbitals in drawn order, 64 walkers")
     wl = make_config(3, n_walk=64, raw_orbital_order=True)
     ev = evaluator(wl)
