@@ -387,6 +387,107 @@ __device__ bool lane_gauss_jordan(int n, int lane, const double *A, double *Xo, 
     return true;
 }
 
+// The reference elimination of one spin by one wave (lane = 0..63): the
+// scaled reference matrix A (in Q) inverted by Gauss-Jordan into X, ln|det|
+// and sign, one residual-correction step, the conditioning flag and
+// grad~D0/D0.  A singular reference flags the pair for the fallback.
+__device__ __forceinline__ void reference_tail(const KernelArgs &a, int w, int sp, int lane,
+                                               const double *Q, double *Xl, double *Rl,
+                                               double *gsc, const int *emax, const int *occl) {
+    const int M = a.M, N = a.N, nm = a.nmax, nn = nm * nm;
+    const SpinDev &S = a.sp[sp];
+    const int n = S.n;
+    const size_t ws = (size_t)w * 2 + sp;
+    const double *A = Q + sp * 5 * nn;
+    double *X = Xl + sp * nn, *Rm = Rl + sp * nn;
+    double la = 0.0, sg = 1.0;
+    const bool ok = lane_gauss_jordan(n, lane, A, X, gsc + sp * (2 * kMaxN + 2), la, sg);
+    if (lane == 0) a.wk.Kmax[ws] = INT_MIN;
+    if (!ok) {
+        if (lane == 0) {
+            a.wk.flag[ws] = 2;
+            a.wk.logdet0[ws] = 0.0;
+            a.wk.sign0[ws] = 1.0;
+        }
+        return;
+    }
+    if (lane == 0) {
+        int sx = 0;
+        for (int c = 0; c < n; ++c) {
+            const int E = emax[sp * M + occl[sp * kMaxN + c]];
+            sx += E == INT_MIN ? 0 : E;  // an all-zero column has scale 0
+        }
+        a.wk.logdet0[ws] = la + (double)sx * 0.69314718055994530942;
+        a.wk.sign0[ws] = sg;
+    }
+    wave_lds_sync();
+    // one residual-correction step: X <- X + X (I - A X); the n-term dot
+    // products are unrolled so that their LDS reads are in flight together
+#pragma unroll
+    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
+        const int idx = lane + 64 * t;
+        if (idx < n * n) {
+            const int i = idx / n, j = idx - i * n;
+            double u = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+            for (int k = 0; k < kMaxN; ++k)
+                if (k < n) u -= A[i * n + k] * X[k * n + j];
+            Rm[idx] = u;
+        }
+    }
+    wave_lds_sync();
+    double xr[kMaxN * kMaxN / 64];
+#pragma unroll
+    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
+        const int idx = lane + 64 * t;
+        if (idx < n * n) {
+            const int i = idx / n, j = idx - i * n;
+            double u = X[idx];
+#pragma unroll
+            for (int k = 0; k < kMaxN; ++k)
+                if (k < n) u += X[i * n + k] * Rm[k * n + j];
+            xr[t] = u;
+        }
+    }
+    wave_lds_sync();
+    double *Xg = a.wk.X + ws * nn;
+#pragma unroll
+    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
+        const int idx = lane + 64 * t;
+        if (idx < n * n) {
+            X[idx] = xr[t];
+            Xg[idx] = xr[t];
+        }
+    }
+    wave_lds_sync();
+    // conditioning: kappa_1 = ||A||_1 ||X||_1 (largest column sums)
+    double ca = 0.0, cx = 0.0;
+    if (lane < n) {
+#pragma unroll
+        for (int i = 0; i < kMaxN; ++i)
+            if (i < n) {
+                ca += fabs(A[i * n + lane]);
+                cx += fabs(X[i * n + lane]);
+            }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        ca = fmax(ca, __shfl_xor(ca, off, 64));
+        cx = fmax(cx, __shfl_xor(cx, off, 64));
+    }
+    if (lane == 0) a.wk.flag[ws] = (ca * cx <= a.kappa_max) ? 0 : 1;  // NaN -> fallback
+    // grad~_e D0 / D0 = sum_c X[c][e] grad~ Phi'[e][occ0[c]]
+    if (lane < 4 * n) {
+        const int e = lane >> 2, q = lane & 3;
+        const double *G = Q + (sp * 5 + 1 + q) * nn;
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < kMaxN; ++c)
+            if (c < n) t += X[c * n + e] * G[e * n + c];
+        a.wk.g0[((size_t)w * N + S.e0 + e) * 4 + q] = t;
+    }
+}
+
 }  // namespace
 
 __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
@@ -470,9 +571,10 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
     if (tid < N) r2s[tid] = rx * rx + ry * ry + rz * rz;
     __syncthreads();
     double *phig = a.wk.phi + (size_t)w * N * 5 * M;
-    // orbitals and derivatives, written once (unscaled)
-    for (int idx = tid; idx < N * M; idx += kBlock) {
-        const int e = idx / M, m = idx - e * M;
+    // orbital m and its derivatives at electron e, written once (unscaled),
+    // with the column's largest exponent and, for a reference column, the
+    // copy in Q
+    auto orbital_at = [&](int e, int m) {
         const int set = (nsets == 2 && e >= nup) ? 1 : 0;  // the down electrons' own orbitals
         double o[5];
         if (stage_prim) orbital5_tab<true>(nullptr, p_al + set * MP, p_cf + set * MP,
@@ -491,119 +593,71 @@ __global__ void __launch_bounds__(kBlock) k_reference(KernelArgs a) {
 #pragma unroll
             for (int q = 0; q < 5; ++q) Q[(sp * 5 + q) * nn + el * n + c] = o[q];
         }
-    }
-    __syncthreads();
+    };
+    // the other orbitals of every electron (those outside its spin's
+    // reference), in chunks of 64 (electron, orbital) pairs that each wave
+    // takes from a counter in LDS until none are left
+    __shared__ int next_pair;
+    auto other_orbitals = [&]() {
+        const int lane = tid & 63;
+        for (;;) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&next_pair, 64);
+            base = __builtin_amdgcn_readfirstlane(base);
+            if (base >= N * M) break;
+            const int idx = base + lane;
+            if (idx < N * M) {
+                const int e = idx / M, m = idx - e * M;
+                if (slot[(e >= nup ? M : 0) + m] < 0) orbital_at(e, m);
+            }
+        }
+    };
     // power-of-two column scales E[sigma][m] (0 for an all-zero column)
-    for (int i = tid; i < 2 * M; i += kBlock) {
-        const int E = (emax[i] == INT_MIN) ? 0 : emax[i];
-        emax[i] = E;
-        a.wk.E[(size_t)w * 2 * M + i] = E;
-    }
+    auto write_scales = [&]() {
+        for (int i = tid; i < 2 * M; i += kBlock) {
+            const int E = (emax[i] == INT_MIN) ? 0 : emax[i];
+            emax[i] = E;
+            a.wk.E[(size_t)w * 2 * M + i] = E;
+        }
+    };
     if (a.method == MDET_METHOD_SM_CHAIN) {  // the chain needs the orbitals and scales only
+        for (int idx = tid; idx < N * M; idx += kBlock) orbital_at(idx / M, idx % M);
+        __syncthreads();
+        write_scales();
         if (tid < 2) a.wk.Kmax[(size_t)w * 2 + tid] = INT_MIN;
         if (w == 0 && tid < 4) a.wk.smstat[tid] = 0ull;
         return;
+    }
+    // the reference columns first (every electron at its spin's n reference
+    // orbitals): their scales are then complete, and the two spins' reference
+    // eliminations (waves 0 and 1) run while waves 2 and 3 evaluate the rest,
+    // which waves 0 and 1 join when done
+    if (tid == 0) next_pair = 0;
+    {
+        const int nd = nocc - nup, pu = nup * nup;
+        for (int idx = tid; idx < pu + nd * nd; idx += kBlock) {
+            const bool dn = idx >= pu;
+            const int j = dn ? idx - pu : idx, nsp = dn ? nd : nup;
+            const int e = (dn ? nup : 0) + j / nsp, c = j - (j / nsp) * nsp;
+            orbital_at(e, occl[(dn ? kMaxN : 0) + c]);
+        }
     }
     __syncthreads();
     for (int i = tid; i < 10 * nn; i += kBlock) {
         const int sp = i / (5 * nn), r = i % nn;
         const int n = a.sp[sp].n;
-        if (r < n * n) Q[i] *= pow2(-emax[sp * M + occl[sp * kMaxN + r % n]]);
+        if (r < n * n) {
+            const int E = emax[sp * M + occl[sp * kMaxN + r % n]];
+            Q[i] *= pow2(-(E == INT_MIN ? 0 : E));
+        }
     }
     __syncthreads();
-    // one wave per spin from here on
-    const int sp = tid >> 6, lane = tid & 63;
-    if (sp > 1) return;
-    const SpinDev S = a.sp[sp];
-    const int n = S.n;
-    const size_t ws = (size_t)w * 2 + sp;
-    const double *A = Q + sp * 5 * nn;
-    double *X = Xl + sp * nn, *Rm = Rl + sp * nn;
-    double la = 0.0, sg = 1.0;
-    bool ok = true;
-    ok = lane_gauss_jordan(n, lane, A, X, gsc + sp * (2 * kMaxN + 2), la, sg);
-    if (lane == 0) a.wk.Kmax[ws] = INT_MIN;
-    if (!ok) {
-        if (lane == 0) {
-            a.wk.flag[ws] = 2;
-            a.wk.logdet0[ws] = 0.0;
-            a.wk.sign0[ws] = 1.0;
-        }
-        return;
-    }
-    if (lane == 0) {
-        int sx = 0;
-        for (int c = 0; c < n; ++c) sx += emax[sp * M + occl[sp * kMaxN + c]];
-        a.wk.logdet0[ws] = la + (double)sx * 0.69314718055994530942;
-        a.wk.sign0[ws] = sg;
-    }
-    wave_lds_sync();
-    // one residual-correction step: X <- X + X (I - A X); the n-term dot
-    // products are unrolled so that their LDS reads are in flight together
-#pragma unroll
-    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
-        const int idx = lane + 64 * t;
-        if (idx < n * n) {
-            const int i = idx / n, j = idx - i * n;
-            double u = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-            for (int k = 0; k < kMaxN; ++k)
-                if (k < n) u -= A[i * n + k] * X[k * n + j];
-            Rm[idx] = u;
-        }
-    }
-    wave_lds_sync();
-    double xr[kMaxN * kMaxN / 64];
-#pragma unroll
-    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
-        const int idx = lane + 64 * t;
-        if (idx < n * n) {
-            const int i = idx / n, j = idx - i * n;
-            double u = X[idx];
-#pragma unroll
-            for (int k = 0; k < kMaxN; ++k)
-                if (k < n) u += X[i * n + k] * Rm[k * n + j];
-            xr[t] = u;
-        }
-    }
-    wave_lds_sync();
-    double *Xg = a.wk.X + ws * nn;
-#pragma unroll
-    for (int t = 0; t < kMaxN * kMaxN / 64; ++t) {
-        const int idx = lane + 64 * t;
-        if (idx < n * n) {
-            X[idx] = xr[t];
-            Xg[idx] = xr[t];
-        }
-    }
-    wave_lds_sync();
-    // conditioning: kappa_1 = ||A||_1 ||X||_1 (largest column sums)
-    double ca = 0.0, cx = 0.0;
-    if (lane < n) {
-#pragma unroll
-        for (int i = 0; i < kMaxN; ++i)
-            if (i < n) {
-                ca += fabs(A[i * n + lane]);
-                cx += fabs(X[i * n + lane]);
-            }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        ca = fmax(ca, __shfl_xor(ca, off, 64));
-        cx = fmax(cx, __shfl_xor(cx, off, 64));
-    }
-    if (lane == 0) a.wk.flag[ws] = (ca * cx <= a.kappa_max) ? 0 : 1;  // NaN -> fallback
-    // grad~_e D0 / D0 = sum_c X[c][e] grad~ Phi'[e][occ0[c]]
-    if (lane < 4 * n) {
-        const int e = lane >> 2, q = lane & 3;
-        const double *G = Q + (sp * 5 + 1 + q) * nn;
-        double t = 0.0;
-#pragma unroll
-        for (int c = 0; c < kMaxN; ++c)
-            if (c < n) t += X[c * n + e] * G[e * n + c];
-        a.wk.g0[((size_t)w * N + S.e0 + e) * 4 + q] = t;
-    }
+    if (tid < 128) reference_tail(a, w, tid >> 6, tid & 63, Q, Xl, Rl, gsc, emax, occl);
+    other_orbitals();
+    __syncthreads();
+    write_scales();
 }
+
 
 namespace {
 
